@@ -1,0 +1,243 @@
+/*
+ * tc.h -- C ABI of libtc, triangle centrality on AMD Instinct MI355X (gfx950).
+ *
+ * Triangle centrality (Burkhardt, "Triangle Centrality", arXiv 2105.00110,
+ * Definition 1 in Sec. "Formulation"):
+ *
+ *   TC(v) = ( 1/3 Σ_{u ∈ N△[v]} △(u) + Σ_{w ∈ N(v) \ N△(v)} △(w) ) / △(G)
+ *
+ * for a simple undirected graph, where △(v) counts triangles at v, △(G)
+ * triangles in the graph, N△(v) = {u ∈ N(v) : N(u) ∩ N(v) ≠ ∅} is the
+ * triangle neighbourhood and N△[v] = N△(v) ∪ {v} (Sec. "Notation").
+ *
+ * The library returns, all exactly:
+ *   tri[v]      △(v)                                           uint64 [n]
+ *   support[e]  triangles on canonical edge e, i.e. the value
+ *               of the graph triangle matrix T = A² ∘ A at
+ *               that edge (Sec. "Algebraic Form")              uint64 [m]
+ *   triG        △(G)                                           uint64 [1] (or [G] for a batch)
+ *   num[v]      3·△(G)·TC(v) =  △(v) + Σ_{u ∈ N△(v)} △(u)
+ *                             + 3 Σ_{w ∈ N(v)\N△(v)} △(w)      uint64 [n]
+ *   tc[v]       (double)num[v] / (double)(3·△(G)): one IEEE-754
+ *               binary64 division, round to nearest even;
+ *               0.0 for every v when △(G) = 0                  double [n]
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Vertices are int32 ids 0..n-1 (the paper labels them 1..n; ids here
+ *   are 0-based, n is explicit and isolated vertices are kept).
+ * - Input pairs (src[i], dst[i]) are undirected.  Self-loops are dropped
+ *   and repeated pairs, in either direction, count once: the graph is
+ *   "symmetrized, weights and loops removed" (Sec. "Comparison").
+ * - Canonical edges: u < v, sorted lexicographically by (u, v).  support[e]
+ *   and tc_get_edges() use this order.  Internal orderings never leak.
+ * - mem_kind: TC_MEM_HOST (pageable or pinned host memory) or
+ *   TC_MEM_DEVICE (device memory of the current HIP device).
+ * - stream: a hipStream_t passed as void*; NULL is the legacy default
+ *   stream.  Device work is enqueued on it.  Calls that must learn a size
+ *   on the host (the edge count after deduplication) synchronise it.
+ * - Ownership: the caller owns every input and output buffer and must keep
+ *   inputs alive until the call returns (host inputs) or the stream has
+ *   passed the call's work (device inputs).  The library owns a tc_graph
+ *   and all its device memory until tc_graph_destroy().
+ * - Errors: every function returns a tc_status; nothing throws across the
+ *   ABI.  On an error no output is written and *out is left NULL.
+ * - Threading: distinct handles may be used from distinct host threads;
+ *   one handle must not be used concurrently.
+ */
+#ifndef TC_H_
+#define TC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tc_graph tc_graph;
+
+typedef enum tc_status {
+    TC_OK = 0,
+    TC_TRIANGLE_FREE = 1,       /* informational: △(G) = 0, tc[] = 0       */
+    TC_ERR_INVALID_ARG = -1,    /* NULL pointer, negative size, bad kind   */
+    TC_ERR_VERTEX_RANGE = -2,   /* an id outside [0, n)                     */
+    TC_ERR_OOM = -3,            /* device allocation failed                 */
+    TC_ERR_DEVICE = -4,         /* a HIP runtime call failed                */
+    TC_ERR_OVERFLOW = -5,       /* a result would not fit its type          */
+    TC_ERR_BUDGET = -6,         /* request larger than the caller's budget  */
+    TC_ERR_NOT_COMPUTED = -7,   /* results requested before tc_compute()    */
+    TC_ERR_UNSUPPORTED = -8     /* size beyond the library's index types    */
+} tc_status;
+
+#define TC_MEM_HOST 0
+#define TC_MEM_DEVICE 1
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t tc_version(void);
+
+/* Static text for a status code. */
+const char *tc_status_string(int32_t status);
+
+/* ------------------------------------------------------------------------
+ * Tuning knobs of the counting step.  They change the schedule only, never
+ * a result: every valid setting yields bit-identical outputs.
+ *   light_max_dplus  rows whose higher-ordered neighbourhood N_H(v) has at
+ *                    most this many entries are intersected by one
+ *                    wavefront each; larger rows by a whole workgroup.
+ *                    Range 2..1024.
+ *   heavy_block      workgroup size of the heavy-row kernel: 64..1024,
+ *                    a multiple of 64.
+ *   light_block      workgroup size of the light-row kernel: 64..1024,
+ *                    a multiple of 64 (one row per wavefront).
+ *   lds_max_entries  largest per-row LDS hash table of the heavy kernel
+ *                    (power of two, 1024..16384); rows needing more are
+ *                    probed by binary search in device memory instead.
+ * ---------------------------------------------------------------------- */
+typedef struct tc_tuning {
+    int32_t light_max_dplus;
+    int32_t heavy_block;
+    int32_t light_block;
+    int32_t lds_max_entries;
+} tc_tuning;
+
+/* Writes the built-in defaults to *t. */
+tc_status tc_tuning_default(tc_tuning *t);
+
+/* ------------------------------------------------------------------------
+ * Graph construction.
+ *
+ * tc_graph_from_edges: builds the deduplicated symmetric graph from
+ *   num_pairs undirected pairs.  Any id outside [0, n) gives
+ *   TC_ERR_VERTEX_RANGE and no handle.  n = 0 with num_pairs = 0 is a valid
+ *   empty graph.  Limits: n < 2^31, num_pairs < 2^32.
+ *
+ * tc_graph_from_csr: same, from a CSR adjacency row_ptr[n+1] (int64,
+ *   row_ptr[0] = 0, non-decreasing) and col[row_ptr[n]].  Every stored entry
+ *   (v, col[k]) is taken as an undirected pair, so one-sided and symmetric
+ *   CSRs give the same graph; loops and duplicates are dropped as above.
+ * ---------------------------------------------------------------------- */
+tc_status tc_graph_from_edges(const int32_t *src, const int32_t *dst, int64_t num_pairs,
+                              int32_t n, int32_t mem_kind, void *stream, tc_graph **out);
+
+tc_status tc_graph_from_csr(const int64_t *row_ptr, const int32_t *col, int32_t n,
+                            int32_t mem_kind, void *stream, tc_graph **out);
+
+/* ------------------------------------------------------------------------
+ * Batched construction: num_graphs independent graphs in one handle.
+ *   graph_pair_off[G+1]  graph g owns pairs graph_pair_off[g] ..
+ *                        graph_pair_off[g+1]-1 of src/dst
+ *   graph_vtx_off[G+1]   graph g owns n_g = graph_vtx_off[g+1] -
+ *                        graph_vtx_off[g] vertices
+ * Pair ids are LOCAL to their graph (0..n_g-1).  Results are laid out as
+ * for one graph over the concatenated vertex range (vertex graph_vtx_off[g]
+ * + i is local vertex i of graph g); canonical edges are grouped by graph
+ * in graph order (tc_batch_edge_offsets); triG has one entry per graph and
+ * tc[v] divides by 3·△ of v's own graph.  Offsets are host arrays.
+ * ---------------------------------------------------------------------- */
+tc_status tc_batch_create(const int32_t *src, const int32_t *dst, const int64_t *graph_pair_off,
+                          const int64_t *graph_vtx_off, int32_t num_graphs, int32_t mem_kind,
+                          void *stream, tc_graph **out);
+
+/* Number of graphs in the handle (1 for a single graph). */
+int32_t tc_num_graphs(const tc_graph *g);
+
+/* Host array edge_off[G+1]: graph g's canonical edges are edge_off[g] ..
+ * edge_off[g+1]-1 of the handle's edge order. */
+tc_status tc_batch_edge_offsets(const tc_graph *g, int64_t *edge_off);
+
+/* ------------------------------------------------------------------------
+ * Computation: triangle counting on the degree-ordered orientation
+ * (Sec. "Algorithm": each triangle found once, from its lowest-ordered
+ * vertex, with the ordering π of Sec. "Notation"), per-edge support, △(v),
+ * △(G), then Algorithm 2's aggregation and the quotient.  Asynchronous on
+ * `stream`.  Returns TC_TRIANGLE_FREE (after computing) when △(G) = 0 for
+ * a single graph; for a batch, the status is TC_OK and per-graph △(G) = 0
+ * shows in triG.  tc_compute_tuned uses explicit knobs (NULL = defaults).
+ * ---------------------------------------------------------------------- */
+tc_status tc_compute(tc_graph *g, void *stream);
+tc_status tc_compute_tuned(tc_graph *g, const tc_tuning *tuning, void *stream);
+
+int64_t tc_num_vertices(const tc_graph *g);   /* n (sum over a batch); -1 if g is NULL */
+int64_t tc_num_edges(const tc_graph *g);      /* m after deduplication; -1 if g is NULL */
+
+/* Canonical edges: u[e] < v[e], e = 0..m-1.  Either pointer may be NULL. */
+tc_status tc_get_edges(const tc_graph *g, int32_t *u, int32_t *v, int32_t mem_kind,
+                       void *stream);
+
+/* Results of the last tc_compute.  Any output pointer may be NULL.  Sizes:
+ * tri[n], support[m], triG[num_graphs], num[n], tc[n].  With TC_MEM_HOST
+ * the call returns after the copies completed (it synchronises stream). */
+tc_status tc_get_results(const tc_graph *g, uint64_t *tri, uint64_t *support, uint64_t *triG,
+                         uint64_t *num, double *tc, int32_t mem_kind, void *stream);
+
+/* Device bytes currently held by the handle. */
+tc_status tc_graph_device_bytes(const tc_graph *g, int64_t *bytes);
+
+/* Estimate of the peak device bytes tc_graph_from_edges + tc_compute need
+ * for num_pairs pairs over n vertices (an upper bound), for admission
+ * control by callers with a memory budget. */
+int64_t tc_estimate_device_bytes(int64_t num_pairs, int32_t n);
+
+/* Releases the handle and its device memory (NULL is a no-op).  Waits for
+ * work still queued on the handle's last stream. */
+void tc_graph_destroy(tc_graph *g);
+
+/* ------------------------------------------------------------------------
+ * Ranking (the "who is most important" question of Sec. "Comparison"):
+ * the k vertices of largest tc, ties broken by smaller vertex id, written
+ * in rank order to vertices[k] (int32) and, if not NULL, values[k].  For a
+ * batch, ranks over all vertices of all graphs.  Requires tc_compute.
+ * k is clamped to n; *k_out receives the count written.
+ * ---------------------------------------------------------------------- */
+tc_status tc_top_k(const tc_graph *g, int32_t k, int32_t *vertices, double *values,
+                   int32_t *k_out, int32_t mem_kind, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Instrumentation (measurement only; results are unaffected).
+ *
+ * tc_set_profiling(on): from now on, handles record HIP events on the
+ *   caller's stream around each stage of tc_graph_from_edges / _from_csr /
+ *   tc_batch_create and tc_compute.  Process-wide switch.
+ * tc_get_stage_ms: device milliseconds of each stage of the handle's last
+ *   build and last compute, ms[TC_NUM_STAGES] in the order below (stages
+ *   that did not run read 0).  Synchronises on the recorded events.
+ *   Returns TC_ERR_NOT_COMPUTED if profiling was off for that work.
+ * tc_get_work_stats: exact work measures of the degree-ordered orientation
+ *   (Sec. "Algorithm", Lemma 1 bounds the same sums), computed on the
+ *   device from the handle's oriented graph on `stream`, stats[
+ *   TC_NUM_WORK_STATS] in the order below.  The candidate sums are
+ *   Σ_{v→u} |N_H(u)| over the oriented edges whose low end v falls in each
+ *   bin of the last tc_compute (light / heavy / huge); merge work is
+ *   Σ_{v→u} (|N_H(v)| + |N_H(u)|); wedges Σ_v C(|N_H(v)|, 2); the edge
+ *   counts are the oriented edges owned by each bin's rows.
+ * ---------------------------------------------------------------------- */
+#define TC_NUM_STAGES 9
+enum {
+    TC_STAGE_CSR_BUILD = 0,   /* dedup + symmetric CSR                  */
+    TC_STAGE_DEGREE_RANK = 1, /* degree ordering                        */
+    TC_STAGE_ORIENT = 2,      /* oriented CSR over ranks                */
+    TC_STAGE_BIN = 3,         /* row binning by |N_H(v)|                */
+    TC_STAGE_COUNT_LIGHT = 4, /* intersection, wavefront per row        */
+    TC_STAGE_COUNT_HEAVY = 5, /* intersection, workgroup per row (LDS)  */
+    TC_STAGE_COUNT_HUGE = 6,  /* intersection, device-memory probe      */
+    TC_STAGE_TRI = 7,         /* support per edge, tri(v), triG         */
+    TC_STAGE_AGGREGATE = 8    /* Algorithm 2 sums + quotient            */
+};
+#define TC_NUM_WORK_STATS 15
+enum {
+    TC_STAT_N = 0, TC_STAT_M = 1, TC_STAT_MAX_DPLUS = 2,
+    TC_STAT_ROWS_LIGHT = 3, TC_STAT_ROWS_HEAVY = 4, TC_STAT_ROWS_HUGE = 5,
+    TC_STAT_CAND_LIGHT = 6, TC_STAT_CAND_HEAVY = 7, TC_STAT_CAND_HUGE = 8,
+    TC_STAT_MERGE_WORK = 9, TC_STAT_WEDGES = 10, TC_STAT_TRIANGLES = 11,
+    TC_STAT_EDGES_LIGHT = 12, TC_STAT_EDGES_HEAVY = 13, TC_STAT_EDGES_HUGE = 14
+};
+
+tc_status tc_set_profiling(int32_t on);
+tc_status tc_get_stage_ms(const tc_graph *g, double *ms);
+tc_status tc_get_work_stats(tc_graph *g, int64_t *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H_ */

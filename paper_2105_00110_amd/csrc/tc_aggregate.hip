@@ -1,0 +1,280 @@
+// Triangle counts per vertex, Algorithm 2's aggregation and the quotient.
+//
+//  * support moves from oriented slots to canonical edges (its output order);
+//  * tri(v) = 1/2 Σ_{u ∈ N(v)} sup(v,u), the quoted theorem of the "Algebraic
+//    Form" section (each triangle at v puts 1 on two of v's edges); the same
+//    pass records, per symmetric slot, whether the edge has support: that is
+//    u ∈ N△(v), since N△(v) = supp T_v (Proposition 2's proof);
+//  * triG = 1/3 Σ_v tri(v) per graph;
+//  * Algorithm 2 over each row: x = tri(v) + Σ_{u ∈ N△(v)} tri(u),
+//    s = Σ_{u ∈ N(v)} tri(u), y = s - x + tri(v), and Definition 1 times
+//    3·triG is num = x + 3y = tri(v) + Σ_u tri(u)·(1 if u ∈ N△(v) else 3),
+//    accumulated in that last form so every term is non-negative;
+//  * tc = (double)num / (double)(3·triG), one IEEE division (0 if triG = 0).
+//
+// Rows are processed by 16-lane groups (four per wavefront) so that short
+// rows do not idle a whole wavefront; rows longer than BIG_DEG go to a
+// second kernel with a workgroup per row.
+#include "tc_internal.h"
+
+namespace {
+
+constexpr int BK = 256;
+constexpr int GS = 16;            // lanes per row in the small-row kernels
+constexpr int64_t BIG_DEG = 4096;  // rows above this use a workgroup
+
+static inline unsigned grid_for(int64_t n, int block = BK) {
+    int64_t g = tc_div_up(n, block);
+    if (g < 1) g = 1;
+    if (g > 0x7FFFFFFF) g = 0x7FFFFFFF;
+    return (unsigned)g;
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T x) {
+#pragma unroll
+    for (int off = GS / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, TC_WAVE);
+    return x;
+}
+
+template <typename T>
+__device__ T block_sum(T x, T *red) {
+    x = tc_wave_sum(x);
+    const int w = threadIdx.x / TC_WAVE;
+    if (__lane_id() == 0) red[w] = x;
+    __syncthreads();
+    T t = 0;
+    for (int i = 0; i < (int)(blockDim.x / TC_WAVE); ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ int32_t graph_of(const int64_t *__restrict__ vtx_off, int32_t G,
+                                            int64_t v) {
+    int32_t lo = 0, hi = G - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (vtx_off[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_scatter_sup(int64_t m, const uint32_t *__restrict__ o2e,
+                              const uint32_t *__restrict__ osup, uint32_t *__restrict__ esup) {
+    GRID_STRIDE(k, m) esup[o2e[k]] = osup[k];
+}
+
+// tri(v) and the triangle-neighbour flag of each slot, small rows.
+__global__ void k_tri_small(int32_t n, const int64_t *__restrict__ row_ptr,
+                            const uint32_t *__restrict__ sym2e, const uint32_t *__restrict__ esup,
+                            uint8_t *__restrict__ flag, uint64_t *__restrict__ tri,
+                            uint32_t *__restrict__ err) {
+    const int sub = threadIdx.x % GS;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GS);
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GS; v < n; v += groups) {
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        if (e - b > BIG_DEG) continue;
+        uint64_t acc = 0;
+        for (int64_t p = b + sub; p < e; p += GS) {
+            uint32_t sp = esup[sym2e[p]];
+            flag[p] = sp != 0;
+            acc += sp;
+        }
+        acc = group_sum(acc);
+        if (sub == 0) {
+            if (acc & 1) atomicOr(err, 2u);
+            tri[v] = acc >> 1;
+        }
+    }
+}
+
+__global__ void k_tri_big(const int32_t *__restrict__ big, int64_t nbig,
+                          const int64_t *__restrict__ row_ptr, const uint32_t *__restrict__ sym2e,
+                          const uint32_t *__restrict__ esup, uint8_t *__restrict__ flag,
+                          uint64_t *__restrict__ tri, uint32_t *__restrict__ err) {
+    __shared__ uint64_t red[16];
+    for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+        const int32_t v = big[i];
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        uint64_t acc = 0;
+        for (int64_t p = b + threadIdx.x; p < e; p += blockDim.x) {
+            uint32_t sp = esup[sym2e[p]];
+            flag[p] = sp != 0;
+            acc += sp;
+        }
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0) {
+            if (acc & 1) atomicOr(err, 2u);
+            tri[v] = acc >> 1;
+        }
+    }
+}
+
+// Σ tri over each graph's vertex range (block-level pre-reduction when the
+// block's vertices lie in one graph).
+__global__ void k_tri_sum(int32_t n, const uint64_t *__restrict__ tri,
+                          const int64_t *__restrict__ vtx_off, int32_t G,
+                          unsigned long long *__restrict__ sums) {
+    __shared__ uint64_t red[16];
+    const int64_t per_block = (int64_t)blockDim.x * 8;
+    for (int64_t base = (int64_t)blockIdx.x * per_block; base < n; base += (int64_t)gridDim.x * per_block) {
+        int64_t last = base + per_block - 1;
+        if (last >= n) last = n - 1;
+        const int32_t g0 = vtx_off ? graph_of(vtx_off, G, base) : 0;
+        const int32_t g1 = vtx_off ? graph_of(vtx_off, G, last) : 0;
+        if (g0 == g1) {
+            uint64_t acc = 0;
+            for (int64_t v = base + threadIdx.x; v <= last; v += blockDim.x) acc += tri[v];
+            acc = block_sum(acc, red);
+            if (threadIdx.x == 0 && acc) atomicAdd(&sums[g0], (unsigned long long)acc);
+        } else {
+            for (int64_t v = base + threadIdx.x; v <= last; v += blockDim.x) {
+                uint64_t t = tri[v];
+                if (t) atomicAdd(&sums[graph_of(vtx_off, G, v)], (unsigned long long)t);
+            }
+        }
+    }
+}
+
+__global__ void k_tri_finish(int32_t G, uint64_t *__restrict__ triG, uint32_t *__restrict__ err) {
+    GRID_STRIDE(g, G) {
+        uint64_t s = triG[g];
+        if (s % 3) atomicOr(err, 4u);
+        uint64_t t = s / 3;
+        if (t > ~0ull / 3) atomicOr(err, 8u);
+        triG[g] = t;
+    }
+}
+
+__device__ __forceinline__ double quotient(uint64_t num, uint64_t tg) {
+    // one correctly rounded binary64 division of two exactly converted
+    // integers (both below 2^53 in practice; the conversion rounds to
+    // nearest even otherwise, as it does on the host)
+    return tg == 0 ? 0.0 : __ddiv_rn((double)num, (double)(3 * tg));
+}
+
+__global__ void k_num_small(int32_t n, const int64_t *__restrict__ row_ptr,
+                            const int32_t *__restrict__ col, const uint8_t *__restrict__ flag,
+                            const uint64_t *__restrict__ tri, const uint64_t *__restrict__ triG,
+                            const int64_t *__restrict__ vtx_off, int32_t G,
+                            uint64_t *__restrict__ num, double *__restrict__ tcv) {
+    const int sub = threadIdx.x % GS;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GS);
+    for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GS; v < n; v += groups) {
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        if (e - b > BIG_DEG) continue;
+        uint64_t acc = 0;
+        for (int64_t p = b + sub; p < e; p += GS) {
+            uint64_t t = tri[col[p]];
+            acc += flag[p] ? t : 3 * t;
+        }
+        acc = group_sum(acc);
+        if (sub == 0) {
+            uint64_t x = acc + tri[v];
+            num[v] = x;
+            uint64_t tg = triG[vtx_off ? graph_of(vtx_off, G, v) : 0];
+            tcv[v] = quotient(x, tg);
+        }
+    }
+}
+
+__global__ void k_num_big(const int32_t *__restrict__ big, int64_t nbig,
+                          const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                          const uint8_t *__restrict__ flag, const uint64_t *__restrict__ tri,
+                          const uint64_t *__restrict__ triG, const int64_t *__restrict__ vtx_off,
+                          int32_t G, uint64_t *__restrict__ num, double *__restrict__ tcv) {
+    __shared__ uint64_t red[16];
+    for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+        const int32_t v = big[i];
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        uint64_t acc = 0;
+        for (int64_t p = b + threadIdx.x; p < e; p += blockDim.x) {
+            uint64_t t = tri[col[p]];
+            acc += flag[p] ? t : 3 * t;
+        }
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0) {
+            uint64_t x = acc + tri[v];
+            num[v] = x;
+            uint64_t tg = triG[vtx_off ? graph_of(vtx_off, G, v) : 0];
+            tcv[v] = quotient(x, tg);
+        }
+    }
+}
+
+__global__ void k_big_flags(int32_t n, const int64_t *__restrict__ row_ptr, uint32_t *__restrict__ f) {
+    GRID_STRIDE(v, n) f[v] = (row_ptr[v + 1] - row_ptr[v]) > BIG_DEG ? 1u : 0u;
+}
+
+__global__ void k_big_write(int32_t n, const int64_t *__restrict__ row_ptr,
+                            const uint32_t *__restrict__ pos, int32_t *__restrict__ out) {
+    GRID_STRIDE(v, n) if ((row_ptr[v + 1] - row_ptr[v]) > BIG_DEG) out[pos[v]] = (int32_t)v;
+}
+
+}  // namespace
+
+tc_status tc_aggregate(tc_graph *g, hipStream_t s) {
+    const int32_t n = g->n;
+    const int64_t m = g->m;
+    const int32_t G = g->num_graphs;
+    const int64_t nn = n > 0 ? n : 1;
+    if (!g->esup) TC_TRY(tc_graph_alloc(g, &g->esup, m, s));
+    if (!g->flag) TC_TRY(tc_graph_alloc(g, &g->flag, 2 * m, s));
+    if (!g->tri) TC_TRY(tc_graph_alloc(g, &g->tri, nn, s));
+    if (!g->num) TC_TRY(tc_graph_alloc(g, &g->num, nn, s));
+    if (!g->tcv) TC_TRY(tc_graph_alloc(g, &g->tcv, nn, s));
+    const int64_t *voff = G > 1 ? g->vtx_off : nullptr;
+    TC_HIP(hipMemsetAsync(g->triG, 0, sizeof(uint64_t) * G, s));
+    if (n == 0) {
+        tc_prof_mark(g, 9, s);
+        tc_prof_mark(g, 10, s);
+        return TC_OK;
+    }
+
+    tc_scratch tmp(s);
+    uint32_t *pos = nullptr, *tot = nullptr;
+    int32_t *big = nullptr;
+    TC_TRY(tmp.get(&pos, nn));
+    TC_TRY(tmp.get(&tot, 1));
+    TC_TRY(tmp.get(&big, nn));
+    k_big_flags<<<grid_for(n), BK, 0, s>>>(n, g->row_ptr, pos);
+    TC_LAUNCHED();
+    TC_TRY(tc_scan_u32(pos, pos, n, tot, s));
+    k_big_write<<<grid_for(n), BK, 0, s>>>(n, g->row_ptr, pos, big);
+    TC_LAUNCHED();
+    uint32_t hbig = 0;
+    TC_HIP(hipMemcpyAsync(&hbig, tot, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    const int64_t nbig = hbig;
+
+    if (m > 0) {
+        k_scatter_sup<<<grid_for(m), BK, 0, s>>>(m, g->o2e, g->osup, g->esup);
+        TC_LAUNCHED();
+    }
+    const unsigned small_grid = grid_for((int64_t)n * GS);
+    k_tri_small<<<small_grid, BK, 0, s>>>(n, g->row_ptr, g->sym2e, g->esup, g->flag, g->tri, g->err);
+    TC_LAUNCHED();
+    if (nbig > 0) {
+        k_tri_big<<<(unsigned)(nbig < 65536 ? nbig : 65536), 1024, 0, s>>>(
+            big, nbig, g->row_ptr, g->sym2e, g->esup, g->flag, g->tri, g->err);
+        TC_LAUNCHED();
+    }
+    k_tri_sum<<<grid_for(n, BK * 8), BK, 0, s>>>(n, g->tri, voff, G, (unsigned long long *)g->triG);
+    TC_LAUNCHED();
+    k_tri_finish<<<grid_for(G), BK, 0, s>>>(G, g->triG, g->err);
+    TC_LAUNCHED();
+    tc_prof_mark(g, 9, s);
+    k_num_small<<<small_grid, BK, 0, s>>>(n, g->row_ptr, g->col, g->flag, g->tri, g->triG, voff, G,
+                                          g->num, g->tcv);
+    TC_LAUNCHED();
+    if (nbig > 0) {
+        k_num_big<<<(unsigned)(nbig < 65536 ? nbig : 65536), 1024, 0, s>>>(
+            big, nbig, g->row_ptr, g->col, g->flag, g->tri, g->triG, voff, G, g->num, g->tcv);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 10, s);
+    return TC_OK;
+}

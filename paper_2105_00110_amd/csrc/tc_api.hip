@@ -1,0 +1,527 @@
+// The extern "C" boundary of libtc (declared in include/tc.h): argument
+// checks, host/device staging, handle lifetime, and the order of stages.
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "tc_internal.h"
+
+#define TC_VERSION 10000
+
+// ---------------------------------------------------------------------------
+// Memory
+// ---------------------------------------------------------------------------
+tc_status tc_map_hip_error(hipError_t e) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return TC_ERR_OOM;
+    return TC_ERR_DEVICE;
+}
+
+static bool g_profiling = false;
+
+bool tc_profiling_on() { return g_profiling; }
+
+void tc_prof_mark(tc_graph *g, int idx, hipStream_t s) {
+    if (!g->prof || idx < 0 || idx >= TC_PROF_MARKS) return;
+    if (!g->prof_ev[idx] && hipEventCreate(&g->prof_ev[idx]) != hipSuccess) {
+        g->prof_ev[idx] = nullptr;
+        return;
+    }
+    (void)hipEventRecord(g->prof_ev[idx], s);
+    if (idx == 3) g->prof_build = true;
+    if (idx == 10) g->prof_compute = true;
+}
+
+static std::mutex g_pool_mu;
+static bool g_pool_ready[64];
+
+static void pool_setup(int dev) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (dev < 0 || dev >= 64 || g_pool_ready[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = ~0ull;  // keep freed blocks cached in the pool
+        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    g_pool_ready[dev] = true;
+}
+
+tc_status tc_dev_alloc(void **p, size_t bytes, hipStream_t s) {
+    int dev = 0;
+    TC_HIP(hipGetDevice(&dev));
+    pool_setup(dev);
+    *p = nullptr;
+    hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return tc_map_hip_error(e);
+    }
+    return TC_OK;
+}
+
+void tc_dev_free(void *p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels of the boundary
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int BK = 256;
+
+static inline unsigned grid_for(int64_t n, int block = BK) {
+    int64_t g = tc_div_up(n, block);
+    if (g < 1) g = 1;
+    if (g > 0x7FFFFFFF) g = 0x7FFFFFFF;
+    return (unsigned)g;
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ void k_widen(const uint32_t *__restrict__ a, int64_t n, uint64_t *__restrict__ out) {
+    GRID_STRIDE(i, n) out[i] = a[i];
+}
+
+// CSR -> pairs: entry k belongs to the last row v with row_ptr[v] <= k.
+__global__ void k_csr_check(const int64_t *__restrict__ rp, int32_t n, uint32_t *__restrict__ err) {
+    GRID_STRIDE(v, n) {
+        if (rp[v + 1] < rp[v]) atomicOr(err, 1u);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && rp[0] != 0) atomicOr(err, 1u);
+}
+
+__global__ void k_csr_expand(const int64_t *__restrict__ rp, int32_t n, int64_t nnz,
+                             int32_t *__restrict__ src) {
+    GRID_STRIDE(k, nnz) {
+        int32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            int32_t mid = (int32_t)(((int64_t)lo + hi + 1) >> 1);
+            if (rp[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        src[k] = lo;
+    }
+}
+
+// tc ≥ 0, so the bit pattern orders like the value; the complement sorts
+// descending, and a stable sort over id order breaks ties by smaller id.
+__global__ void k_topk_keys(const double *__restrict__ tcv, int32_t n, uint64_t *__restrict__ key,
+                            uint32_t *__restrict__ id) {
+    GRID_STRIDE(v, n) {
+        key[v] = ~(uint64_t)__double_as_longlong(tcv[v]);
+        id[v] = (uint32_t)v;
+    }
+}
+
+__global__ void k_topk_out(const uint32_t *__restrict__ id, const double *__restrict__ tcv,
+                           int32_t k, int32_t *__restrict__ verts, double *__restrict__ vals) {
+    GRID_STRIDE(i, k) {
+        uint32_t v = id[i];
+        verts[i] = (int32_t)v;
+        if (vals) vals[i] = tcv[v];
+    }
+}
+
+__global__ void k_edge_offsets(const int32_t *__restrict__ eu, int64_t m,
+                               const int64_t *__restrict__ vtx_off, int32_t G,
+                               int64_t *__restrict__ eoff) {
+    GRID_STRIDE(gi, (int64_t)G + 1) {
+        const int64_t first = vtx_off[gi];
+        int64_t lo = 0, hi = m;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (eu[mid] < first) lo = mid + 1; else hi = mid;
+        }
+        eoff[gi] = lo;
+    }
+}
+
+tc_status copy_out(void *dst, const void *src, size_t bytes, int32_t mem_kind, hipStream_t s) {
+    if (bytes == 0) return TC_OK;
+    TC_HIP(hipMemcpyAsync(dst, src, bytes,
+                          mem_kind == TC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                          s));
+    return TC_OK;
+}
+
+void free_graph_arrays(tc_graph *g, hipStream_t s) {
+    void *arrs[] = {g->eu,   g->ev,   g->row_ptr, g->col,  g->sym2e, g->rank, g->perm,
+                    g->orp,  g->ocol, g->o2e,     g->osup, g->esup,  g->flag, g->tri,
+                    g->num,  g->tcv,  g->triG,    g->vtx_off, g->err, g->bin_rows};
+    for (void *p : arrs) tc_dev_free(p, s);
+}
+
+tc_status new_graph(int32_t n, int32_t num_graphs, tc_graph **out) {
+    tc_graph *g = new (std::nothrow) tc_graph();
+    if (!g) return TC_ERR_OOM;
+    TC_HIP(hipGetDevice(&g->device));
+    g->n = n;
+    g->num_graphs = num_graphs;
+    g->prof = g_profiling;
+    int b = tc_bits_for(n > 1 ? (uint64_t)(n - 1) : 1);
+    g->bits = b < 1 ? 1 : b;
+    *out = g;
+    return TC_OK;
+}
+
+tc_status finish_build(tc_graph *g, hipStream_t s) {
+    TC_TRY(tc_orient(g, s));
+    return TC_OK;
+}
+
+tc_status build_common(tc_graph *g, const int32_t *src, const int32_t *dst, int64_t P,
+                       int32_t mem_kind, const int64_t *h_pair_off, hipStream_t s) {
+    tc_scratch tmp(s);
+    tc_prof_mark(g, 0, s);
+    const int32_t *d_src = src, *d_dst = dst;
+    if (mem_kind == TC_MEM_HOST && P > 0) {
+        int32_t *a = nullptr, *b = nullptr;
+        TC_TRY(tmp.get(&a, P));
+        TC_TRY(tmp.get(&b, P));
+        TC_HIP(hipMemcpyAsync(a, src, sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
+        TC_HIP(hipMemcpyAsync(b, dst, sizeof(int32_t) * P, hipMemcpyHostToDevice, s));
+        d_src = a;
+        d_dst = b;
+    }
+    int64_t *d_pair_off = nullptr;
+    if (h_pair_off) {
+        TC_TRY(tmp.get(&d_pair_off, g->num_graphs + 1));
+        TC_HIP(hipMemcpyAsync(d_pair_off, h_pair_off, sizeof(int64_t) * (g->num_graphs + 1),
+                              hipMemcpyHostToDevice, s));
+    }
+    TC_TRY(tc_build_from_pairs(g, d_src, d_dst, P, g->vtx_off, d_pair_off, g->num_graphs, s));
+    TC_TRY(finish_build(g, s));
+    return TC_OK;
+}
+
+bool valid_kind(int32_t k) { return k == TC_MEM_HOST || k == TC_MEM_DEVICE; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Public entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t tc_version(void) { return TC_VERSION; }
+
+const char *tc_status_string(int32_t s) {
+    switch (s) {
+        case TC_OK: return "ok";
+        case TC_TRIANGLE_FREE: return "triangle-free graph: TC is 0 everywhere";
+        case TC_ERR_INVALID_ARG: return "invalid argument";
+        case TC_ERR_VERTEX_RANGE: return "vertex id outside [0, n)";
+        case TC_ERR_OOM: return "device out of memory";
+        case TC_ERR_DEVICE: return "HIP runtime error";
+        case TC_ERR_OVERFLOW: return "result does not fit its integer type";
+        case TC_ERR_BUDGET: return "request exceeds the memory budget";
+        case TC_ERR_NOT_COMPUTED: return "results requested before tc_compute";
+        case TC_ERR_UNSUPPORTED: return "size beyond the library's index types";
+        default: return "unknown status";
+    }
+}
+
+tc_status tc_graph_from_edges(const int32_t *src, const int32_t *dst, int64_t num_pairs, int32_t n,
+                              int32_t mem_kind, void *stream, tc_graph **out) {
+    if (!out) return TC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n < 0 || num_pairs < 0 || !valid_kind(mem_kind)) return TC_ERR_INVALID_ARG;
+    if (num_pairs > 0 && (!src || !dst)) return TC_ERR_INVALID_ARG;
+    if (num_pairs >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    tc_graph *g = nullptr;
+    TC_TRY(new_graph(n, 1, &g));
+    g->last_stream = s;
+    tc_status st = build_common(g, src, dst, num_pairs, mem_kind, nullptr, s);
+    if (st < 0) {
+        tc_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return TC_OK;
+}
+
+tc_status tc_graph_from_csr(const int64_t *row_ptr, const int32_t *col, int32_t n,
+                            int32_t mem_kind, void *stream, tc_graph **out) {
+    if (!out) return TC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n < 0 || !row_ptr || !valid_kind(mem_kind)) return TC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    tc_scratch tmp(s);
+    const int64_t *d_rp = row_ptr;
+    int64_t nnz = 0;
+    if (mem_kind == TC_MEM_HOST) {
+        if (row_ptr[0] != 0) return TC_ERR_INVALID_ARG;
+        for (int32_t v = 0; v < n; ++v)
+            if (row_ptr[v + 1] < row_ptr[v]) return TC_ERR_INVALID_ARG;
+        nnz = row_ptr[n];
+        int64_t *a = nullptr;
+        TC_TRY(tmp.get(&a, (int64_t)n + 1));
+        TC_HIP(hipMemcpyAsync(a, row_ptr, sizeof(int64_t) * ((int64_t)n + 1), hipMemcpyHostToDevice, s));
+        d_rp = a;
+    } else {
+        uint32_t *err = nullptr;
+        TC_TRY(tmp.get(&err, 1));
+        TC_HIP(hipMemsetAsync(err, 0, 4, s));
+        k_csr_check<<<grid_for(n > 0 ? n : 1), BK, 0, s>>>(d_rp, n, err);
+        TC_LAUNCHED();
+        uint32_t h_err = 0;
+        TC_HIP(hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, s));
+        TC_HIP(hipMemcpyAsync(&nnz, d_rp + n, 8, hipMemcpyDeviceToHost, s));
+        TC_HIP(hipStreamSynchronize(s));
+        if (h_err) return TC_ERR_INVALID_ARG;
+    }
+    if (nnz < 0) return TC_ERR_INVALID_ARG;
+    if (nnz > 0 && !col) return TC_ERR_INVALID_ARG;
+    if (nnz >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
+    const int32_t *d_col = col;
+    if (mem_kind == TC_MEM_HOST && nnz > 0) {
+        int32_t *c = nullptr;
+        TC_TRY(tmp.get(&c, nnz));
+        TC_HIP(hipMemcpyAsync(c, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+        d_col = c;
+    }
+    int32_t *d_src = nullptr;
+    if (nnz > 0) {
+        TC_TRY(tmp.get(&d_src, nnz));
+        k_csr_expand<<<grid_for(nnz), BK, 0, s>>>(d_rp, n, nnz, d_src);
+        TC_LAUNCHED();
+    }
+    tc_graph *g = nullptr;
+    TC_TRY(new_graph(n, 1, &g));
+    g->last_stream = s;
+    tc_prof_mark(g, 0, s);
+    tc_status st = tc_build_from_pairs(g, d_src, d_col, nnz, nullptr, nullptr, 1, s);
+    if (st >= 0) st = finish_build(g, s);
+    if (st < 0) {
+        tc_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return TC_OK;
+}
+
+tc_status tc_batch_create(const int32_t *src, const int32_t *dst, const int64_t *graph_pair_off,
+                          const int64_t *graph_vtx_off, int32_t num_graphs, int32_t mem_kind,
+                          void *stream, tc_graph **out) {
+    if (!out) return TC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (num_graphs < 1 || !graph_pair_off || !graph_vtx_off || !valid_kind(mem_kind))
+        return TC_ERR_INVALID_ARG;
+    if (graph_pair_off[0] != 0 || graph_vtx_off[0] != 0) return TC_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < num_graphs; ++i)
+        if (graph_pair_off[i + 1] < graph_pair_off[i] || graph_vtx_off[i + 1] < graph_vtx_off[i])
+            return TC_ERR_INVALID_ARG;
+    const int64_t P = graph_pair_off[num_graphs];
+    const int64_t N = graph_vtx_off[num_graphs];
+    if (N > 0x7FFFFFFFll - 1) return TC_ERR_UNSUPPORTED;
+    if (P >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
+    if (P > 0 && (!src || !dst)) return TC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    tc_graph *g = nullptr;
+    TC_TRY(new_graph((int32_t)N, num_graphs, &g));
+    g->last_stream = s;
+    tc_status st = TC_OK;
+    g->h_vtx_off = (int64_t *)malloc(sizeof(int64_t) * (num_graphs + 1));
+    g->h_edge_off = (int64_t *)calloc(num_graphs + 1, sizeof(int64_t));
+    if (!g->h_vtx_off || !g->h_edge_off) st = TC_ERR_OOM;
+    if (st == TC_OK) {
+        memcpy(g->h_vtx_off, graph_vtx_off, sizeof(int64_t) * (num_graphs + 1));
+        st = tc_graph_alloc(g, &g->vtx_off, num_graphs + 1, s);
+    }
+    if (st == TC_OK) {
+        hipError_t e = hipMemcpyAsync(g->vtx_off, graph_vtx_off, sizeof(int64_t) * (num_graphs + 1),
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = tc_map_hip_error(e);
+    }
+    if (st == TC_OK) st = build_common(g, src, dst, P, mem_kind, graph_pair_off, s);
+    if (st == TC_OK) {
+        // canonical edges are sorted by their smaller (global) end, so graph
+        // gi's edges start at the first edge whose smaller end is >= its
+        // first vertex
+        tc_scratch tmp(s);
+        int64_t *d_eoff = nullptr;
+        st = tmp.get(&d_eoff, num_graphs + 1);
+        if (st == TC_OK) {
+            k_edge_offsets<<<grid_for(num_graphs + 1), BK, 0, s>>>(g->eu, g->m, g->vtx_off,
+                                                                   num_graphs, d_eoff);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(g->h_edge_off, d_eoff, sizeof(int64_t) * (num_graphs + 1),
+                                   hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = tc_map_hip_error(e);
+        }
+    }
+    if (st < 0) {
+        tc_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return TC_OK;
+}
+
+int32_t tc_num_graphs(const tc_graph *g) { return g ? g->num_graphs : -1; }
+
+tc_status tc_batch_edge_offsets(const tc_graph *g, int64_t *edge_off) {
+    if (!g || !edge_off) return TC_ERR_INVALID_ARG;
+    if (g->num_graphs == 1 && !g->h_edge_off) {
+        edge_off[0] = 0;
+        edge_off[1] = g->m;
+        return TC_OK;
+    }
+    memcpy(edge_off, g->h_edge_off, sizeof(int64_t) * (g->num_graphs + 1));
+    return TC_OK;
+}
+
+tc_status tc_compute_tuned(tc_graph *g, const tc_tuning *tuning, void *stream) {
+    if (!g) return TC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    g->last_stream = s;
+    g->computed = false;
+    g->prof_compute = false;
+    tc_prof_mark(g, 4, s);
+    TC_TRY(tc_count(g, tuning, s));
+    TC_TRY(tc_aggregate(g, s));
+    uint32_t h_err = 0;
+    uint64_t tg = 0;
+    TC_HIP(hipMemcpyAsync(&h_err, g->err, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipMemcpyAsync(&tg, g->triG, 8, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (h_err & 8u) return TC_ERR_OVERFLOW;
+    if (h_err) return TC_ERR_DEVICE;  // an internal parity check failed
+    g->computed = true;
+    g->status = (g->num_graphs == 1 && tg == 0) ? TC_TRIANGLE_FREE : TC_OK;
+    return (tc_status)g->status;
+}
+
+tc_status tc_compute(tc_graph *g, void *stream) { return tc_compute_tuned(g, nullptr, stream); }
+
+int64_t tc_num_vertices(const tc_graph *g) { return g ? g->n : -1; }
+int64_t tc_num_edges(const tc_graph *g) { return g ? g->m : -1; }
+
+tc_status tc_get_edges(const tc_graph *g, int32_t *u, int32_t *v, int32_t mem_kind, void *stream) {
+    if (!g || !valid_kind(mem_kind)) return TC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (u) TC_TRY(copy_out(u, g->eu, sizeof(int32_t) * g->m, mem_kind, s));
+    if (v) TC_TRY(copy_out(v, g->ev, sizeof(int32_t) * g->m, mem_kind, s));
+    if (mem_kind == TC_MEM_HOST) TC_HIP(hipStreamSynchronize(s));
+    return TC_OK;
+}
+
+tc_status tc_get_results(const tc_graph *g, uint64_t *tri, uint64_t *support, uint64_t *triG,
+                         uint64_t *num, double *tc, int32_t mem_kind, void *stream) {
+    if (!g || !valid_kind(mem_kind)) return TC_ERR_INVALID_ARG;
+    if (!g->computed) return TC_ERR_NOT_COMPUTED;
+    hipStream_t s = (hipStream_t)stream;
+    tc_scratch tmp(s);
+    if (tri) TC_TRY(copy_out(tri, g->tri, sizeof(uint64_t) * g->n, mem_kind, s));
+    if (num) TC_TRY(copy_out(num, g->num, sizeof(uint64_t) * g->n, mem_kind, s));
+    if (tc) TC_TRY(copy_out(tc, g->tcv, sizeof(double) * g->n, mem_kind, s));
+    if (triG) TC_TRY(copy_out(triG, g->triG, sizeof(uint64_t) * g->num_graphs, mem_kind, s));
+    if (support && g->m > 0) {
+        uint64_t *dst = support;
+        if (mem_kind == TC_MEM_HOST) TC_TRY(tmp.get(&dst, g->m));
+        k_widen<<<grid_for(g->m), BK, 0, s>>>(g->esup, g->m, dst);
+        TC_LAUNCHED();
+        if (mem_kind == TC_MEM_HOST) TC_TRY(copy_out(support, dst, sizeof(uint64_t) * g->m, mem_kind, s));
+    }
+    if (mem_kind == TC_MEM_HOST) TC_HIP(hipStreamSynchronize(s));
+    return TC_OK;
+}
+
+tc_status tc_graph_device_bytes(const tc_graph *g, int64_t *bytes) {
+    if (!g || !bytes) return TC_ERR_INVALID_ARG;
+    *bytes = (int64_t)g->bytes;
+    return TC_OK;
+}
+
+int64_t tc_estimate_device_bytes(int64_t P, int32_t n) {
+    if (P < 0 || n < 0) return -1;
+    // resident: edges 8m, sym CSR 8(n+1) + 16m, ranks 8n, oriented 8(n+1) +
+    // 8m, supports 8m, flags 2m, results 24n; peak temporaries of the build:
+    // pair keys 16P + flags 4P (+ staged host pairs 8P).
+    const int64_t m = P;
+    return 8 * m + 8 * (int64_t)n + 16 * m + 8 * (int64_t)n + 8 * (int64_t)n + 8 * m + 8 * m +
+           2 * m + 24 * (int64_t)n + 28 * P + (64ll << 20);
+}
+
+void tc_graph_destroy(tc_graph *g) {
+    if (!g) return;
+    hipStream_t s = g->last_stream;
+    free_graph_arrays(g, s);
+    (void)hipStreamSynchronize(s);
+    for (int i = 0; i < TC_PROF_MARKS; ++i)
+        if (g->prof_ev[i]) (void)hipEventDestroy(g->prof_ev[i]);
+    free(g->h_vtx_off);
+    free(g->h_edge_off);
+    delete g;
+}
+
+tc_status tc_top_k(const tc_graph *g, int32_t k, int32_t *vertices, double *values, int32_t *k_out,
+                   int32_t mem_kind, void *stream) {
+    if (!g || k < 0 || !vertices || !valid_kind(mem_kind)) return TC_ERR_INVALID_ARG;
+    if (!g->computed) return TC_ERR_NOT_COMPUTED;
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t n = g->n;
+    if (k > n) k = n;
+    if (k_out) *k_out = k;
+    if (k == 0) return TC_OK;
+    tc_scratch tmp(s);
+    uint64_t *key = nullptr, *key2 = nullptr;
+    uint32_t *id = nullptr, *id2 = nullptr;
+    TC_TRY(tmp.get(&key, n));
+    TC_TRY(tmp.get(&key2, n));
+    TC_TRY(tmp.get(&id, n));
+    TC_TRY(tmp.get(&id2, n));
+    k_topk_keys<<<grid_for(n), BK, 0, s>>>(g->tcv, n, key, id);
+    TC_LAUNCHED();
+    TC_TRY(tc_sort_u64_u32(&key, &id, &key2, &id2, n, 64, s));
+    int32_t *dv = vertices;
+    double *dval = values;
+    if (mem_kind == TC_MEM_HOST) {
+        TC_TRY(tmp.get(&dv, k));
+        if (values) TC_TRY(tmp.get(&dval, k));
+    }
+    k_topk_out<<<grid_for(k), BK, 0, s>>>(id, g->tcv, k, dv, dval);
+    TC_LAUNCHED();
+    if (mem_kind == TC_MEM_HOST) {
+        TC_TRY(copy_out(vertices, dv, sizeof(int32_t) * k, mem_kind, s));
+        if (values) TC_TRY(copy_out(values, dval, sizeof(double) * k, mem_kind, s));
+        TC_HIP(hipStreamSynchronize(s));
+    }
+    return TC_OK;
+}
+
+tc_status tc_set_profiling(int32_t on) {
+    g_profiling = on != 0;
+    return TC_OK;
+}
+
+tc_status tc_get_stage_ms(const tc_graph *g, double *ms) {
+    if (!g || !ms) return TC_ERR_INVALID_ARG;
+    if (!g->prof_build && !g->prof_compute) return TC_ERR_NOT_COMPUTED;
+    static const int from[TC_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7, 8, 9};
+    static const int to[TC_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8, 9, 10};
+    for (int i = 0; i < TC_NUM_STAGES; ++i) {
+        ms[i] = 0.0;
+        bool build = to[i] <= 3;
+        if ((build && !g->prof_build) || (!build && !g->prof_compute)) continue;
+        hipEvent_t a = g->prof_ev[from[i]], b = g->prof_ev[to[i]];
+        if (!a || !b) continue;
+        TC_HIP(hipEventSynchronize(b));
+        float t = 0.f;
+        TC_HIP(hipEventElapsedTime(&t, a, b));
+        ms[i] = t;
+    }
+    return TC_OK;
+}
+
+tc_status tc_get_work_stats(tc_graph *g, int64_t *stats, void *stream) {
+    if (!g || !stats) return TC_ERR_INVALID_ARG;
+    return tc_work_stats(g, stats, (hipStream_t)stream);
+}
+
+}  // extern "C"

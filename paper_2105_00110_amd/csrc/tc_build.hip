@@ -1,0 +1,363 @@
+// Graph build on the device: normalisation into the canonical edge list
+// and the symmetric CSR, the degree ordering, and the degree-ordered
+// orientation.
+//
+//  1. Pack every pair as the 64-bit key (min << bits) | max (self-loops
+//     become a sentinel above every real key), radix sort, keep first
+//     occurrences: canonical edges (u < v) in lexicographic order.
+//  2. Symmetric CSR in original ids.  Row x is [smaller neighbours] then
+//     [larger neighbours]; the larger ones are the run of canonical edges
+//     with eu = x (already sorted), the smaller ones come from a stable
+//     sort of (ev, e) -- the transpose -- which lists them by increasing eu.
+//  3. Degree ordering π (Sec. "Notation"): position in the order by
+//     (degree, id), from a stable sort of degrees over ids in id order.
+//  4. Orientation: each canonical edge becomes (π(low), π(high)); a sort of
+//     these packed keys yields the oriented CSR whose row r lists the
+//     higher-ordered neighbours N_H of the rank-r vertex, ascending.  This
+//     is the paper's split of N(v) into N_L(v) | N_H(v) (Lemma 1's proof),
+//     stored as its own compact array for the counting kernels.
+#include "tc_internal.h"
+
+namespace {
+
+constexpr int BK = 256;
+
+static inline unsigned grid_for(int64_t n, int block = BK) {
+    int64_t g = tc_div_up(n, block);
+    if (g < 1) g = 1;
+    if (g > 0x7FFFFFFF) g = 0x7FFFFFFF;
+    return (unsigned)g;
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// Pair -> packed canonical key.  For a batch, pair i belongs to the graph g
+// with pair_off[g] <= i < pair_off[g+1]; its ids are local and get the
+// graph's first global vertex id added.
+__global__ void k_make_keys(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                            int64_t P, int32_t n, int bits, const int64_t *__restrict__ pair_off,
+                            const int64_t *__restrict__ vtx_off, int32_t G,
+                            uint64_t *__restrict__ keys, uint32_t *__restrict__ err) {
+    const uint64_t sentinel = (bits >= 32) ? ~0ull : ((1ull << (2 * bits)) - 1);
+    GRID_STRIDE(i, P) {
+        int64_t a = src[i], b = dst[i];
+        int64_t lim = n, base = 0;
+        if (pair_off != nullptr) {
+            int32_t lo = 0, hi = G - 1;  // last g with pair_off[g] <= i
+            while (lo < hi) {
+                int32_t mid = (lo + hi + 1) >> 1;
+                if (pair_off[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            base = vtx_off[lo];
+            lim = vtx_off[lo + 1] - base;
+        }
+        uint64_t key;
+        if (a < 0 || a >= lim || b < 0 || b >= lim) {
+            atomicOr(err, 1u);
+            key = sentinel;
+        } else if (a == b) {
+            key = sentinel;
+        } else {
+            uint64_t lo = (uint64_t)((a < b ? a : b) + base), hi = (uint64_t)((a < b ? b : a) + base);
+            key = (lo << bits) | hi;
+        }
+        keys[i] = key;
+    }
+}
+
+__global__ void k_unique_flags(const uint64_t *__restrict__ keys, int64_t P, uint64_t sentinel,
+                               uint32_t *__restrict__ flags) {
+    GRID_STRIDE(i, P) {
+        uint64_t k = keys[i];
+        flags[i] = (k != sentinel && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+    }
+}
+
+__global__ void k_unique_write(const uint64_t *__restrict__ keys, int64_t P, uint64_t sentinel,
+                               int bits, const uint32_t *__restrict__ pos,
+                               int32_t *__restrict__ eu, int32_t *__restrict__ ev) {
+    const uint64_t mask = (1ull << bits) - 1;
+    GRID_STRIDE(i, P) {
+        uint64_t k = keys[i];
+        if (k != sentinel && (i == 0 || keys[i - 1] != k)) {
+            uint32_t p = pos[i];
+            eu[p] = (int32_t)(k >> bits);
+            ev[p] = (int32_t)(k & mask);
+        }
+    }
+}
+
+// Run boundaries of a sorted id sequence: start/end of each present id.
+// start and end must be zeroed first.
+template <typename Get>
+__global__ void k_runs(Get get, int64_t len, uint32_t *__restrict__ start,
+                       uint32_t *__restrict__ end) {
+    GRID_STRIDE(i, len) {
+        uint32_t x = get(i);
+        if (i == 0 || get(i - 1) != x) start[x] = (uint32_t)i;
+        if (i == len - 1 || get(i + 1) != x) end[x] = (uint32_t)(i + 1);
+    }
+}
+
+struct GetI32 {
+    const int32_t *a;
+    __device__ uint32_t operator()(int64_t i) const { return (uint32_t)a[i]; }
+};
+struct GetU32 {
+    const uint32_t *a;
+    __device__ uint32_t operator()(int64_t i) const { return a[i]; }
+};
+struct GetHigh {
+    const uint64_t *a;
+    int bits;
+    __device__ uint32_t operator()(int64_t i) const { return (uint32_t)(a[i] >> bits); }
+};
+
+__global__ void k_degree(int32_t n, const uint32_t *__restrict__ us, const uint32_t *__restrict__ ue,
+                         const uint32_t *__restrict__ ls, const uint32_t *__restrict__ le,
+                         int64_t *__restrict__ deg64, uint32_t *__restrict__ deg32) {
+    GRID_STRIDE(x, n) {
+        uint32_t d = (ue[x] - us[x]) + (le[x] - ls[x]);
+        deg64[x] = d;
+        deg32[x] = d;
+    }
+}
+
+// Smaller neighbours: transposed entry j = (ev, e) sorted by ev.
+__global__ void k_fill_lower(int64_t m, const uint32_t *__restrict__ tkey,
+                             const uint32_t *__restrict__ tval, const uint32_t *__restrict__ lstart,
+                             const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ eu,
+                             int32_t *__restrict__ col, uint32_t *__restrict__ sym2e) {
+    GRID_STRIDE(j, m) {
+        uint32_t x = tkey[j], e = tval[j];
+        int64_t p = row_ptr[x] + (j - (int64_t)lstart[x]);
+        col[p] = eu[e];
+        sym2e[p] = e;
+    }
+}
+
+// Larger neighbours: canonical edge e = (x, v) is the (e - ustart[x])-th.
+__global__ void k_fill_upper(int64_t m, const int32_t *__restrict__ eu,
+                             const int32_t *__restrict__ ev, const uint32_t *__restrict__ ustart,
+                             const uint32_t *__restrict__ lstart, const uint32_t *__restrict__ lend,
+                             const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col,
+                             uint32_t *__restrict__ sym2e) {
+    GRID_STRIDE(e, m) {
+        uint32_t x = (uint32_t)eu[e];
+        int64_t p = row_ptr[x] + (lend[x] - lstart[x]) + (e - (int64_t)ustart[x]);
+        col[p] = ev[e];
+        sym2e[p] = (uint32_t)e;
+    }
+}
+
+__global__ void k_iota(uint32_t *a, int64_t n) {
+    GRID_STRIDE(i, n) a[i] = (uint32_t)i;
+}
+
+__global__ void k_invert(const uint32_t *__restrict__ perm, int32_t n, int32_t *__restrict__ perm_out,
+                         int32_t *__restrict__ rank) {
+    GRID_STRIDE(r, n) {
+        uint32_t v = perm[r];
+        perm_out[r] = (int32_t)v;
+        rank[v] = (int32_t)r;
+    }
+}
+
+__global__ void k_orient_keys(int64_t m, const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+                              const int32_t *__restrict__ rank, int bits, uint64_t *__restrict__ okey,
+                              uint32_t *__restrict__ oval) {
+    GRID_STRIDE(e, m) {
+        uint64_t a = (uint32_t)rank[eu[e]], b = (uint32_t)rank[ev[e]];
+        uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+        okey[e] = (lo << bits) | hi;
+        oval[e] = (uint32_t)e;
+    }
+}
+
+__global__ void k_orient_split(int64_t m, const uint64_t *__restrict__ okey, int bits,
+                               int32_t *__restrict__ ocol) {
+    const uint64_t mask = (1ull << bits) - 1;
+    GRID_STRIDE(k, m) ocol[k] = (int32_t)(okey[k] & mask);
+}
+
+__global__ void k_run_len64(int32_t n, const uint32_t *__restrict__ s, const uint32_t *__restrict__ e,
+                            int64_t *__restrict__ len, uint32_t *__restrict__ maxlen) {
+    GRID_STRIDE(x, n) {
+        uint32_t d = e[x] - s[x];
+        len[x] = d;
+        if (d > 0) atomicMax(maxlen, d);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t P,
+                              const int64_t *d_vtx_off, const int64_t *d_pair_off,
+                              int32_t num_graphs, hipStream_t s) {
+    const int32_t n = g->n;
+    const int bits = g->bits;
+    const uint64_t sentinel = (bits >= 32) ? ~0ull : ((1ull << (2 * bits)) - 1);
+    tc_scratch tmp(s);
+
+    TC_TRY(tc_graph_alloc(g, &g->err, 4, s));
+    TC_HIP(hipMemsetAsync(g->err, 0, 16, s));
+
+    // -- 1. canonical edges ---------------------------------------------------
+    int64_t m = 0;
+    if (P > 0) {
+        uint64_t *keys = nullptr, *keys2 = nullptr;
+        TC_TRY(tmp.get(&keys, P));
+        TC_TRY(tmp.get(&keys2, P));
+        k_make_keys<<<grid_for(P), BK, 0, s>>>(d_src, d_dst, P, n, bits, d_pair_off, d_vtx_off,
+                                               num_graphs, keys, g->err);
+        TC_LAUNCHED();
+        uint32_t h_err = 0;
+        TC_HIP(hipMemcpyAsync(&h_err, g->err, 4, hipMemcpyDeviceToHost, s));
+        TC_HIP(hipStreamSynchronize(s));
+        if (h_err) return TC_ERR_VERTEX_RANGE;
+        TC_TRY(tc_sort_u64(&keys, &keys2, P, 2 * bits, s));
+        uint32_t *pos = nullptr, *d_m = nullptr;
+        TC_TRY(tmp.get(&pos, P));
+        TC_TRY(tmp.get(&d_m, 1));
+        k_unique_flags<<<grid_for(P), BK, 0, s>>>(keys, P, sentinel, pos);
+        TC_LAUNCHED();
+        TC_TRY(tc_scan_u32(pos, pos, P, d_m, s));
+        uint32_t h_m = 0;
+        TC_HIP(hipMemcpyAsync(&h_m, d_m, 4, hipMemcpyDeviceToHost, s));
+        TC_HIP(hipStreamSynchronize(s));
+        m = h_m;
+        TC_TRY(tc_graph_alloc(g, &g->eu, m, s));
+        TC_TRY(tc_graph_alloc(g, &g->ev, m, s));
+        if (m > 0) {
+            k_unique_write<<<grid_for(P), BK, 0, s>>>(keys, P, sentinel, bits, pos, g->eu, g->ev);
+            TC_LAUNCHED();
+        }
+    } else {
+        TC_TRY(tc_graph_alloc(g, &g->eu, 0, s));
+        TC_TRY(tc_graph_alloc(g, &g->ev, 0, s));
+    }
+    g->m = m;
+
+    // -- 2. symmetric CSR -------------------------------------------------------
+    TC_TRY(tc_graph_alloc(g, &g->row_ptr, (int64_t)n + 1, s));
+    TC_TRY(tc_graph_alloc(g, &g->col, 2 * m, s));
+    TC_TRY(tc_graph_alloc(g, &g->sym2e, 2 * m, s));
+    uint32_t *us = nullptr, *ue = nullptr, *ls = nullptr, *le = nullptr, *deg32 = nullptr;
+    int64_t *deg64 = nullptr;
+    int64_t nn = n > 0 ? n : 1;
+    TC_TRY(tmp.get(&us, nn));
+    TC_TRY(tmp.get(&ue, nn));
+    TC_TRY(tmp.get(&ls, nn));
+    TC_TRY(tmp.get(&le, nn));
+    TC_TRY(tmp.get(&deg32, nn));
+    TC_TRY(tmp.get(&deg64, nn));
+    TC_HIP(hipMemsetAsync(us, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemsetAsync(ue, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemsetAsync(ls, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemsetAsync(le, 0, sizeof(uint32_t) * nn, s));
+    uint32_t *tkey = nullptr, *tval = nullptr;
+    if (m > 0) {
+        uint32_t *tkey2 = nullptr, *tval2 = nullptr;
+        TC_TRY(tmp.get(&tkey, m));
+        TC_TRY(tmp.get(&tval, m));
+        TC_TRY(tmp.get(&tkey2, m));
+        TC_TRY(tmp.get(&tval2, m));
+        TC_HIP(hipMemcpyAsync(tkey, g->ev, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
+        k_iota<<<grid_for(m), BK, 0, s>>>(tval, m);
+        TC_LAUNCHED();
+        TC_TRY(tc_sort_u32_u32(&tkey, &tval, &tkey2, &tval2, m, bits, s));
+        k_runs<<<grid_for(m), BK, 0, s>>>(GetI32{g->eu}, m, us, ue);
+        TC_LAUNCHED();
+        k_runs<<<grid_for(m), BK, 0, s>>>(GetU32{tkey}, m, ls, le);
+        TC_LAUNCHED();
+    }
+    if (n > 0) {
+        k_degree<<<grid_for(n), BK, 0, s>>>(n, us, ue, ls, le, deg64, deg32);
+        TC_LAUNCHED();
+        TC_TRY(tc_scan_i64(deg64, g->row_ptr, n, g->row_ptr + n, s));
+    } else {
+        TC_HIP(hipMemsetAsync(g->row_ptr, 0, sizeof(int64_t), s));
+    }
+    if (m > 0) {
+        k_fill_lower<<<grid_for(m), BK, 0, s>>>(m, tkey, tval, ls, g->row_ptr, g->eu, g->col,
+                                                g->sym2e);
+        TC_LAUNCHED();
+        k_fill_upper<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, us, ls, le, g->row_ptr, g->col,
+                                                g->sym2e);
+        TC_LAUNCHED();
+    }
+
+    tc_prof_mark(g, 1, s);
+
+    // -- 3. degree ordering -------------------------------------------------------
+    TC_TRY(tc_graph_alloc(g, &g->rank, nn, s));
+    TC_TRY(tc_graph_alloc(g, &g->perm, nn, s));
+    if (n > 0) {
+        uint32_t *pv = nullptr, *pv2 = nullptr, *dk2 = nullptr;
+        TC_TRY(tmp.get(&pv, nn));
+        TC_TRY(tmp.get(&pv2, nn));
+        TC_TRY(tmp.get(&dk2, nn));
+        k_iota<<<grid_for(n), BK, 0, s>>>(pv, n);
+        TC_LAUNCHED();
+        // degrees are below n, so `bits` bits hold them
+        TC_TRY(tc_sort_u32_u32(&deg32, &pv, &dk2, &pv2, n, bits, s));
+        k_invert<<<grid_for(n), BK, 0, s>>>(pv, n, g->perm, g->rank);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 2, s);
+    return TC_OK;
+}
+
+tc_status tc_orient(tc_graph *g, hipStream_t s) {
+    const int32_t n = g->n;
+    const int64_t m = g->m;
+    const int bits = g->bits;
+    tc_scratch tmp(s);
+    int64_t nn = n > 0 ? n : 1;
+    TC_TRY(tc_graph_alloc(g, &g->orp, nn + 1, s));
+    TC_TRY(tc_graph_alloc(g, &g->ocol, m, s));
+    TC_TRY(tc_graph_alloc(g, &g->o2e, m, s));
+    g->max_dplus = 0;
+    if (m == 0) {
+        TC_HIP(hipMemsetAsync(g->orp, 0, sizeof(int64_t) * (nn + 1), s));
+        tc_prof_mark(g, 3, s);
+        return TC_OK;
+    }
+    uint64_t *okey = nullptr, *okey2 = nullptr;
+    uint32_t *oval2 = nullptr;
+    TC_TRY(tmp.get(&okey, m));
+    TC_TRY(tmp.get(&okey2, m));
+    TC_TRY(tmp.get(&oval2, m));
+    uint32_t *oval = g->o2e;
+    uint32_t *oval_swap = oval2;
+    k_orient_keys<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->rank, bits, okey, oval);
+    TC_LAUNCHED();
+    TC_TRY(tc_sort_u64_u32(&okey, &oval, &okey2, &oval_swap, m, 2 * bits, s));
+    if (oval != g->o2e) {
+        TC_HIP(hipMemcpyAsync(g->o2e, oval, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
+    }
+    k_orient_split<<<grid_for(m), BK, 0, s>>>(m, okey, bits, g->ocol);
+    TC_LAUNCHED();
+    uint32_t *rs = nullptr, *re = nullptr, *d_max = nullptr;
+    int64_t *dplus = nullptr;
+    TC_TRY(tmp.get(&rs, nn));
+    TC_TRY(tmp.get(&re, nn));
+    TC_TRY(tmp.get(&dplus, nn));
+    TC_TRY(tmp.get(&d_max, 1));
+    TC_HIP(hipMemsetAsync(rs, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemsetAsync(re, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemsetAsync(d_max, 0, sizeof(uint32_t), s));
+    k_runs<<<grid_for(m), BK, 0, s>>>(GetHigh{okey, bits}, m, rs, re);
+    TC_LAUNCHED();
+    k_run_len64<<<grid_for(n), BK, 0, s>>>(n, rs, re, dplus, d_max);
+    TC_LAUNCHED();
+    TC_TRY(tc_scan_i64(dplus, g->orp, n, g->orp + n, s));
+    tc_prof_mark(g, 3, s);
+    uint32_t h_max = 0;
+    TC_HIP(hipMemcpyAsync(&h_max, d_max, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    g->max_dplus = (int32_t)h_max;
+    return TC_OK;
+}

@@ -1,0 +1,166 @@
+// Stable LSD radix sort, 8-bit digits, for the graph build.
+//
+// Per digit pass (reduce-then-scan form):
+//   k_radix_hist    each tile of TILE keys counts its 256 digits in LDS and
+//                   writes them digit-major: counts[d * tiles + tile];
+//   tc_scan_u32     exclusive scan of the counts gives, for every (digit,
+//                   tile), the first output position of that tile's keys
+//                   with that digit (smaller digits first, then earlier
+//                   tiles: this is what makes the pass stable);
+//   k_radix_scatter every wavefront ranks its keys with 8 ballots per item
+//                   (lanes holding the same digit form a 64-bit peer mask;
+//                   the rank is the popcount of lower peers plus the
+//                   wavefront's running count of that digit), wavefronts
+//                   are combined by a per-digit prefix over the block, and
+//                   keys (and values) are written to their final place.
+// Tile element order is (wavefront, item, lane), which equals memory order,
+// so equal digits keep their input order.
+#include "tc_internal.h"
+
+namespace {
+
+constexpr int RB = 8;
+constexpr int RADIX = 1 << RB;
+constexpr int SORT_BLOCK = 256;
+constexpr int SORT_WAVES = SORT_BLOCK / TC_WAVE;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
+
+struct NoVal {};
+
+template <typename K>
+__global__ __launch_bounds__(SORT_BLOCK) void k_radix_hist(const K *__restrict__ keys, int64_t n,
+                                                           int shift, uint32_t *__restrict__ counts,
+                                                           int64_t tiles) {
+    __shared__ uint32_t hist[SORT_WAVES][RADIX];
+    for (int i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_BLOCK) (&hist[0][0])[i] = 0;
+    __syncthreads();
+    int w = threadIdx.x / TC_WAVE;
+    int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        int64_t i = base + it * SORT_BLOCK + threadIdx.x;
+        if (i < n) atomicAdd(&hist[w][(uint32_t)(keys[i] >> shift) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < RADIX; d += SORT_BLOCK) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < SORT_WAVES; ++q) c += hist[q][d];
+        counts[(int64_t)d * tiles + blockIdx.x] = c;
+    }
+}
+
+template <typename K, typename V, bool HAS_VAL>
+__global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
+    const K *__restrict__ kin, const V *__restrict__ vin, K *__restrict__ kout,
+    V *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offsets,
+    int64_t tiles) {
+    __shared__ uint32_t wcnt[SORT_WAVES][RADIX];
+    __shared__ uint32_t gbase[RADIX];
+    for (int i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_BLOCK) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    const int w = threadIdx.x / TC_WAVE;
+    const int lane = __lane_id();
+    const uint64_t lt = tc_lanemask_lt();
+    const int64_t wbase = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * (TC_WAVE * SORT_ITEMS);
+
+    K key[SORT_ITEMS];
+    V val[SORT_ITEMS];
+    uint32_t rnk[SORT_ITEMS];
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        int64_t i = wbase + it * TC_WAVE + lane;
+        bool valid = i < n;
+        key[it] = valid ? kin[i] : (K)0;
+        if constexpr (HAS_VAL) val[it] = valid ? vin[i] : (V)0;
+    }
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        int64_t i = wbase + it * TC_WAVE + lane;
+        bool valid = i < n;
+        uint32_t d = (uint32_t)(key[it] >> shift) & (RADIX - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        uint32_t prior = 0;
+        if (valid) prior = wcnt[w][d];
+        rnk[it] = prior + (uint32_t)__popcll(peers & lt);
+        // the highest peer publishes the new running count of this digit
+        bool last = valid && ((peers >> lane) == 1ull);
+        if (last) wcnt[w][d] = prior + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < RADIX; d += SORT_BLOCK) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < SORT_WAVES; ++q) {
+            uint32_t c = wcnt[q][d];
+            wcnt[q][d] = run;
+            run += c;
+        }
+        gbase[d] = offsets[(int64_t)d * tiles + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SORT_ITEMS; ++it) {
+        int64_t i = wbase + it * TC_WAVE + lane;
+        if (i < n) {
+            uint32_t d = (uint32_t)(key[it] >> shift) & (RADIX - 1);
+            uint32_t pos = gbase[d] + wcnt[w][d] + rnk[it];
+            kout[pos] = key[it];
+            if constexpr (HAS_VAL) vout[pos] = val[it];
+        }
+    }
+}
+
+template <typename K, typename V, bool HAS_VAL>
+tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bits, hipStream_t s) {
+    if (n < 0 || bits < 0 || bits > (int)(8 * sizeof(K))) return TC_ERR_INVALID_ARG;
+    if (n <= 1 || bits == 0) return TC_OK;
+    if (n >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
+    int64_t tiles = tc_div_up(n, SORT_TILE);
+    tc_scratch tmp(s);
+    uint32_t *counts = nullptr;
+    TC_TRY(tmp.get(&counts, tiles * RADIX));
+    for (int shift = 0; shift < bits; shift += RB) {
+        k_radix_hist<K><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(*keys, n, shift, counts, tiles);
+        TC_LAUNCHED();
+        TC_TRY(tc_scan_u32(counts, counts, tiles * RADIX, nullptr, s));
+        k_radix_scatter<K, V, HAS_VAL><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(
+            *keys, HAS_VAL ? *vals : nullptr, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift,
+            counts, tiles);
+        TC_LAUNCHED();
+        K *tk = *keys;
+        *keys = *tkeys;
+        *tkeys = tk;
+        if constexpr (HAS_VAL) {
+            V *tv = *vals;
+            *vals = *tvals;
+            *tvals = tv;
+        }
+    }
+    return TC_OK;
+}
+
+}  // namespace
+
+tc_status tc_sort_u64(uint64_t **keys, uint64_t **tmp_keys, int64_t n, int bits, hipStream_t s) {
+    uint32_t *nv = nullptr, *ntv = nullptr;
+    return radix_sort<uint64_t, uint32_t, false>(keys, &nv, tmp_keys, &ntv, n, bits, s);
+}
+
+tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
+                          uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s) {
+    return radix_sort<uint64_t, uint32_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s);
+}
+
+tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,
+                          uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s) {
+    return radix_sort<uint32_t, uint32_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s);
+}

@@ -1,0 +1,398 @@
+"""Thin ctypes binding of libtc (the C ABI in include/tc.h).
+
+The functions named ``tc_*`` here mirror the C entry points one to one and
+only marshal arguments: every step of the computation runs in libtc's HIP
+kernels.  Buffers are passed as raw pointers: device buffers are torch CUDA
+tensors (PyTorch only allocates memory and provides the stream), host
+buffers are numpy arrays.  There is no fallback: if libtc.so is missing or
+fails to load, every call raises.
+
+``Graph`` wraps a handle for convenience (tests, benchmark, server).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc.so")
+
+TC_OK = 0
+TC_TRIANGLE_FREE = 1
+TC_ERR_INVALID_ARG = -1
+TC_ERR_VERTEX_RANGE = -2
+TC_ERR_OOM = -3
+TC_ERR_DEVICE = -4
+TC_ERR_OVERFLOW = -5
+TC_ERR_BUDGET = -6
+TC_ERR_NOT_COMPUTED = -7
+TC_ERR_UNSUPPORTED = -8
+
+TC_MEM_HOST = 0
+TC_MEM_DEVICE = 1
+
+_lib = None
+
+
+class TCError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = int(status)
+        msg = _lib.tc_status_string(int(status)).decode() if _lib else str(status)
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+class tc_tuning(ctypes.Structure):
+    _fields_ = [("light_max_dplus", ctypes.c_int32), ("heavy_block", ctypes.c_int32),
+                ("light_block", ctypes.c_int32), ("lds_max_entries", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_st = ctypes.c_int32
+
+_SIGS = {
+    "tc_version": (_i32, []),
+    "tc_status_string": (ctypes.c_char_p, [_i32]),
+    "tc_tuning_default": (_st, [ctypes.POINTER(tc_tuning)]),
+    "tc_graph_from_edges": (_st, [_vp, _vp, _i64, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
+    "tc_graph_from_csr": (_st, [_vp, _vp, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
+    "tc_batch_create": (_st, [_vp, _vp, _vp, _vp, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
+    "tc_num_graphs": (_i32, [_vp]),
+    "tc_batch_edge_offsets": (_st, [_vp, _vp]),
+    "tc_compute": (_st, [_vp, _vp]),
+    "tc_compute_tuned": (_st, [_vp, ctypes.POINTER(tc_tuning), _vp]),
+    "tc_num_vertices": (_i64, [_vp]),
+    "tc_num_edges": (_i64, [_vp]),
+    "tc_get_edges": (_st, [_vp, _vp, _vp, _i32, _vp]),
+    "tc_get_results": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "tc_graph_device_bytes": (_st, [_vp, ctypes.POINTER(_i64)]),
+    "tc_estimate_device_bytes": (_i64, [_i64, _i32]),
+    "tc_graph_destroy": (None, [_vp]),
+    "tc_top_k": (_st, [_vp, _i32, _vp, _vp, ctypes.POINTER(_i32), _i32, _vp]),
+    "tc_set_profiling": (_st, [_i32]),
+    "tc_get_stage_ms": (_st, [_vp, _vp]),
+    "tc_get_work_stats": (_st, [_vp, _vp, _vp]),
+}
+
+STAGES = ["csr_build", "degree_rank", "orient", "bin", "count_light", "count_heavy",
+          "count_huge", "tri", "aggregate"]
+WORK_STATS = ["n", "m", "max_dplus", "rows_light", "rows_heavy", "rows_huge", "cand_light",
+              "cand_heavy", "cand_huge", "merge_work", "wedges", "triangles", "edges_light",
+              "edges_heavy", "edges_huge"]
+
+
+def load(path=None):
+    """Load libtc.so (built in-tree by the package build)."""
+    global _lib
+    if _lib is None:
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError(f"libtc.so not found at {p}: build the HIP library first")
+        L = ctypes.CDLL(p)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, where):
+    if status < 0:
+        raise TCError(status, where)
+    return int(status)
+
+
+# ---------------------------------------------------------------------------
+# One-to-one wrappers of the C entry points
+# ---------------------------------------------------------------------------
+def tc_version():
+    return int(load().tc_version())
+
+
+def tc_status_string(status):
+    return load().tc_status_string(int(status)).decode()
+
+
+def tc_tuning_default():
+    t = tc_tuning()
+    _check(load().tc_tuning_default(ctypes.byref(t)), "tc_tuning_default")
+    return t
+
+
+def tc_graph_from_edges(src, dst, num_pairs, n, mem_kind, stream):
+    h = _vp()
+    _check(load().tc_graph_from_edges(src, dst, int(num_pairs), int(n), int(mem_kind), stream,
+                                      ctypes.byref(h)), "tc_graph_from_edges")
+    return h
+
+
+def tc_graph_from_csr(row_ptr, col, n, mem_kind, stream):
+    h = _vp()
+    _check(load().tc_graph_from_csr(row_ptr, col, int(n), int(mem_kind), stream, ctypes.byref(h)),
+           "tc_graph_from_csr")
+    return h
+
+
+def tc_batch_create(src, dst, graph_pair_off, graph_vtx_off, num_graphs, mem_kind, stream):
+    h = _vp()
+    _check(load().tc_batch_create(src, dst, graph_pair_off, graph_vtx_off, int(num_graphs),
+                                  int(mem_kind), stream, ctypes.byref(h)), "tc_batch_create")
+    return h
+
+
+def tc_num_graphs(h):
+    return int(load().tc_num_graphs(h))
+
+
+def tc_batch_edge_offsets(h, edge_off):
+    return _check(load().tc_batch_edge_offsets(h, edge_off), "tc_batch_edge_offsets")
+
+
+def tc_compute(h, stream):
+    return _check(load().tc_compute(h, stream), "tc_compute")
+
+
+def tc_compute_tuned(h, tuning, stream):
+    return _check(load().tc_compute_tuned(h, ctypes.byref(tuning) if tuning is not None else None,
+                                          stream), "tc_compute_tuned")
+
+
+def tc_num_vertices(h):
+    return int(load().tc_num_vertices(h))
+
+
+def tc_num_edges(h):
+    return int(load().tc_num_edges(h))
+
+
+def tc_get_edges(h, u, v, mem_kind, stream):
+    return _check(load().tc_get_edges(h, u, v, int(mem_kind), stream), "tc_get_edges")
+
+
+def tc_get_results(h, tri, support, triG, num, tc, mem_kind, stream):
+    return _check(load().tc_get_results(h, tri, support, triG, num, tc, int(mem_kind), stream),
+                  "tc_get_results")
+
+
+def tc_graph_device_bytes(h):
+    b = _i64(0)
+    _check(load().tc_graph_device_bytes(h, ctypes.byref(b)), "tc_graph_device_bytes")
+    return int(b.value)
+
+
+def tc_estimate_device_bytes(num_pairs, n):
+    return int(load().tc_estimate_device_bytes(int(num_pairs), int(n)))
+
+
+def tc_graph_destroy(h):
+    if h:
+        load().tc_graph_destroy(h)
+
+
+def tc_top_k(h, k, vertices, values, mem_kind, stream):
+    ko = _i32(0)
+    _check(load().tc_top_k(h, int(k), vertices, values, ctypes.byref(ko), int(mem_kind), stream),
+           "tc_top_k")
+    return int(ko.value)
+
+
+def tc_set_profiling(on):
+    return _check(load().tc_set_profiling(1 if on else 0), "tc_set_profiling")
+
+
+def tc_get_stage_ms(h):
+    ms = (ctypes.c_double * len(STAGES))()
+    _check(load().tc_get_stage_ms(h, ctypes.cast(ms, _vp)), "tc_get_stage_ms")
+    return dict(zip(STAGES, list(ms)))
+
+
+def tc_get_work_stats(h, stream):
+    st = (ctypes.c_int64 * len(WORK_STATS))()
+    _check(load().tc_get_work_stats(h, ctypes.cast(st, _vp), stream), "tc_get_work_stats")
+    return dict(zip(WORK_STATS, [int(x) for x in st]))
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper
+# ---------------------------------------------------------------------------
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if _is_torch(x):
+        return x.data_ptr()
+    return x.ctypes.data
+
+
+def current_stream():
+    """hipStream_t of torch's current stream (as an int), or None."""
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Graph:
+    """A libtc handle.  Build with ``from_edges`` / ``from_csr`` / ``batch``."""
+
+    def __init__(self, handle, stream=None):
+        self.h = handle
+        self.stream = stream
+        self.status = None
+
+    # -- construction ---------------------------------------------------------
+    @classmethod
+    def from_edges(cls, src, dst, n, stream=None):
+        dev = _is_torch(src) and src.is_cuda
+        if dev:
+            import torch
+            src = src.to(torch.int32).contiguous()
+            dst = dst.to(torch.int32).contiguous()
+            if stream is None:
+                stream = current_stream()
+        else:
+            src = np.ascontiguousarray(src, np.int32)
+            dst = np.ascontiguousarray(dst, np.int32)
+        h = tc_graph_from_edges(_ptr(src), _ptr(dst), src.shape[0], n,
+                                TC_MEM_DEVICE if dev else TC_MEM_HOST, stream)
+        return cls(h, stream)
+
+    @classmethod
+    def from_csr(cls, row_ptr, col, n, stream=None):
+        dev = _is_torch(row_ptr) and row_ptr.is_cuda
+        if dev:
+            if stream is None:
+                stream = current_stream()
+        else:
+            row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+            col = np.ascontiguousarray(col, np.int32)
+        h = tc_graph_from_csr(_ptr(row_ptr), _ptr(col), n, TC_MEM_DEVICE if dev else TC_MEM_HOST,
+                              stream)
+        return cls(h, stream)
+
+    @classmethod
+    def batch(cls, src, dst, pair_off, vtx_off, stream=None):
+        dev = _is_torch(src) and src.is_cuda
+        if dev and stream is None:
+            stream = current_stream()
+        if not dev:
+            src = np.ascontiguousarray(src, np.int32)
+            dst = np.ascontiguousarray(dst, np.int32)
+        po = np.ascontiguousarray(pair_off, np.int64)
+        vo = np.ascontiguousarray(vtx_off, np.int64)
+        h = tc_batch_create(_ptr(src), _ptr(dst), po.ctypes.data, vo.ctypes.data, po.shape[0] - 1,
+                            TC_MEM_DEVICE if dev else TC_MEM_HOST, stream)
+        return cls(h, stream)
+
+    # -- queries ----------------------------------------------------------------
+    @property
+    def n(self):
+        return tc_num_vertices(self.h)
+
+    @property
+    def m(self):
+        return tc_num_edges(self.h)
+
+    @property
+    def num_graphs(self):
+        return tc_num_graphs(self.h)
+
+    def device_bytes(self):
+        return tc_graph_device_bytes(self.h)
+
+    def compute(self, tuning=None):
+        if tuning is None:
+            self.status = tc_compute(self.h, self.stream)
+        else:
+            t = tuning if isinstance(tuning, tc_tuning) else tuning_from_dict(tuning)
+            self.status = tc_compute_tuned(self.h, t, self.stream)
+        return self.status
+
+    def edges(self):
+        m = self.m
+        u = np.empty(max(m, 1), np.int32)
+        v = np.empty(max(m, 1), np.int32)
+        tc_get_edges(self.h, _ptr(u), _ptr(v), TC_MEM_HOST, self.stream)
+        return u[:m], v[:m]
+
+    def edge_offsets(self):
+        off = np.empty(self.num_graphs + 1, np.int64)
+        tc_batch_edge_offsets(self.h, _ptr(off))
+        return off
+
+    def results(self):
+        """Host copies: dict(tri, support, triG, num, tc)."""
+        n, m, G = self.n, self.m, self.num_graphs
+        out = {
+            "tri": np.empty(max(n, 1), np.uint64),
+            "support": np.empty(max(m, 1), np.uint64),
+            "triG": np.empty(G, np.uint64),
+            "num": np.empty(max(n, 1), np.uint64),
+            "tc": np.empty(max(n, 1), np.float64),
+        }
+        tc_get_results(self.h, _ptr(out["tri"]), _ptr(out["support"]), _ptr(out["triG"]),
+                       _ptr(out["num"]), _ptr(out["tc"]), TC_MEM_HOST, self.stream)
+        out["tri"] = out["tri"][:n]
+        out["support"] = out["support"][:m]
+        out["num"] = out["num"][:n]
+        out["tc"] = out["tc"][:n]
+        return out
+
+    def results_device(self):
+        """Device copies as torch tensors (int64 views of the uint64 data)."""
+        import torch
+        n, m, G = self.n, self.m, self.num_graphs
+        dev = torch.device("cuda")
+        out = {
+            "tri": torch.empty(max(n, 1), dtype=torch.int64, device=dev),
+            "support": torch.empty(max(m, 1), dtype=torch.int64, device=dev),
+            "triG": torch.empty(G, dtype=torch.int64, device=dev),
+            "num": torch.empty(max(n, 1), dtype=torch.int64, device=dev),
+            "tc": torch.empty(max(n, 1), dtype=torch.float64, device=dev),
+        }
+        tc_get_results(self.h, _ptr(out["tri"]), _ptr(out["support"]), _ptr(out["triG"]),
+                       _ptr(out["num"]), _ptr(out["tc"]), TC_MEM_DEVICE, self.stream)
+        return out
+
+    def stage_ms(self):
+        return tc_get_stage_ms(self.h)
+
+    def work_stats(self):
+        return tc_get_work_stats(self.h, self.stream)
+
+    def top_k(self, k):
+        k = min(int(k), self.n)
+        verts = np.empty(max(k, 1), np.int32)
+        vals = np.empty(max(k, 1), np.float64)
+        got = tc_top_k(self.h, k, _ptr(verts), _ptr(vals), TC_MEM_HOST, self.stream)
+        return verts[:got], vals[:got]
+
+    def close(self):
+        if self.h:
+            tc_graph_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tuning_from_dict(d):
+    t = tc_tuning_default()
+    for k, v in d.items():
+        setattr(t, k, int(v))
+    return t

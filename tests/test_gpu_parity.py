@@ -1,0 +1,251 @@
+"""GPU parity: libtc (through its C ABI) against the CPU oracle.
+
+Integer outputs (edges, support, tri, triG, num) must be identical and the
+float64 quotient bit-identical (the same single IEEE division on both
+sides).  Inputs are seeded and shared; no expected value comes from the HIP
+path.
+"""
+import numpy as np
+import pytest
+
+from oracle import native
+from paper_2105_00110_amd import graphgen as gg
+from tests import golden_io
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def run_gpu(tc, src, dst, n, device=True, tuning=None):
+    if device:
+        s = torch.as_tensor(np.ascontiguousarray(src, np.int32)).cuda()
+        d = torch.as_tensor(np.ascontiguousarray(dst, np.int32)).cuda()
+        g = tc.Graph.from_edges(s, d, n)
+    else:
+        g = tc.Graph.from_edges(src, dst, n)
+    st = g.compute(tuning)
+    res = g.results()
+    res["eu"], res["ev"] = g.edges()
+    res["status"] = st
+    res["m"] = g.m
+    g.close()
+    return res
+
+
+def assert_parity(gpu, ref):
+    assert gpu["m"] == ref.m
+    np.testing.assert_array_equal(gpu["eu"], ref.eu)
+    np.testing.assert_array_equal(gpu["ev"], ref.ev)
+    np.testing.assert_array_equal(gpu["support"], ref.sup)
+    np.testing.assert_array_equal(gpu["tri"], ref.tri)
+    assert int(gpu["triG"][0]) == ref.triG
+    np.testing.assert_array_equal(gpu["num"], ref.num)
+    np.testing.assert_array_equal(gpu["tc"].view(np.uint64), ref.tc.view(np.uint64))
+    assert gpu["status"] == ref.status
+
+
+SMALL_FAMILIES = {
+    "K3": lambda: gg.clique(3),
+    "K12": lambda: gg.clique(12),
+    "K200": lambda: gg.clique(200),
+    "bridge_4x6": lambda: gg.bridge_cliques(4, 6),
+    "disjoint_5x4": lambda: gg.disjoint_cliques(5, 4),
+    "chain_6x5": lambda: gg.clique_chain(6, 5)[:3],
+    "ring_5x4": lambda: gg.clique_chain(5, 4, ring=True)[:3],
+    "single_tri": lambda: gg.single_triangle_with_pendants((2, 3, 1)),
+    "er_2000": lambda: gg.er(2000, 0.005, seed=1),
+    "ba_3000": lambda: gg.ba(3000, 8, seed=3),
+    "rmat_s10": lambda: gg.rmat(10, 16, seed=2),
+    "rmat_s14": lambda: gg.rmat(14, 16, seed=5),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SMALL_FAMILIES))
+def test_parity_small_families(tclib, name):
+    src, dst, n = SMALL_FAMILIES[name]()
+    ref = native.o1_definition(src, dst, n)
+    _say(name, "n", n, "pairs", len(src), "device input")
+    assert_parity(run_gpu(tclib, src, dst, n, device=True), ref)
+    _say(name, "host input")
+    assert_parity(run_gpu(tclib, src, dst, n, device=False), ref)
+
+
+@pytest.mark.parametrize("fname", ["fig2_worked_example.txt", "fig1a.txt", "fig1c.txt",
+                                   "fig1d.txt"])
+def test_parity_paper_figures(tclib, fname):
+    src, dst, n, _ = golden_io.load(fname)
+    ref = native.o2_paper(src, dst, n)
+    _say(fname)
+    assert_parity(run_gpu(tclib, src, dst, n), ref)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_parity_er_config(tclib, seed):
+    src, dst, n = gg.er(2000, 0.005, seed=seed)
+    ref = native.o2_paper(src, dst, n)
+    _say("ER G(2000,0.005) seed", seed)
+    assert_parity(run_gpu(tclib, src, dst, n), ref)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_parity_random_tiny(tclib, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 40))
+    P = int(rng.integers(0, 200))
+    src = rng.integers(0, n, P).astype(np.int32)
+    dst = rng.integers(0, n, P).astype(np.int32)
+    ref = native.o1_definition(src, dst, n)
+    _say("tiny seed", seed, "n", n, "P", P)
+    assert_parity(run_gpu(tclib, src, dst, n), ref)
+
+
+TUNINGS = [
+    None,
+    {"light_max_dplus": 2, "heavy_block": 64, "light_block": 64, "lds_max_entries": 16384},
+    {"light_max_dplus": 1024, "heavy_block": 1024, "light_block": 1024, "lds_max_entries": 1024},
+    {"light_max_dplus": 16, "heavy_block": 512, "light_block": 128, "lds_max_entries": 1024},
+]
+
+
+@pytest.mark.parametrize("ti", range(len(TUNINGS)))
+def test_every_schedule_gives_identical_bytes(tclib, ti):
+    # heavy tail (R-MAT) plus a clique large enough for the huge-row path
+    src, dst, n = gg.rmat(13, 16, seed=9)
+    ks, kd, kn = gg.clique(700)
+    src = np.concatenate([src, ks + n]).astype(np.int32)
+    dst = np.concatenate([dst, kd + n]).astype(np.int32)
+    n = n + kn
+    ref = native.o1_definition(src, dst, n)
+    _say("tuning", TUNINGS[ti])
+    assert_parity(run_gpu(tclib, src, dst, n, tuning=TUNINGS[ti]), ref)
+
+
+def test_rmat_s20_full_parity(tclib):
+    src, dst, n = gg.rmat(20, 16, seed=20)
+    _say("R-MAT s20 oracle")
+    ref = native.o1_definition(src, dst, n)
+    _say("R-MAT s20 gpu")
+    assert_parity(run_gpu(tclib, src, dst, n), ref)
+
+
+def test_determinism_two_runs(tclib):
+    src, dst, n = gg.rmat(16, 16, seed=3)
+    _say("determinism s16")
+    a = run_gpu(tclib, src, dst, n)
+    b = run_gpu(tclib, src, dst, n)
+    for k in ("support", "tri", "num", "triG", "eu", "ev"):
+        np.testing.assert_array_equal(a[k], b[k])
+    np.testing.assert_array_equal(a["tc"].view(np.uint64), b["tc"].view(np.uint64))
+
+
+def test_from_csr_matches_edges(tclib):
+    src, dst, n = gg.rmat(12, 16, seed=4)
+    ref = native.o2_paper(src, dst, n)
+    # a one-sided CSR holding every input pair once, duplicates included
+    order = np.lexsort((dst, src))
+    s, d = src[order], dst[order]
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, s + 1, 1)
+    rp = np.cumsum(rp)
+    _say("from_csr host")
+    g = tclib.Graph.from_csr(rp, d, n)
+    st = g.compute()
+    res = g.results()
+    res["eu"], res["ev"] = g.edges()
+    res["status"], res["m"] = st, g.m
+    g.close()
+    assert_parity(res, ref)
+    _say("from_csr device")
+    g = tclib.Graph.from_csr(torch.as_tensor(rp).cuda(), torch.as_tensor(d).cuda(), n)
+    st = g.compute()
+    res = g.results()
+    res["eu"], res["ev"] = g.edges()
+    res["status"], res["m"] = st, g.m
+    g.close()
+    assert_parity(res, ref)
+
+
+def test_degenerate_inputs(tclib):
+    e = np.zeros(0, np.int32)
+    _say("empty n=0")
+    r = run_gpu(tclib, e, e, 0, device=False)
+    assert r["m"] == 0 and r["status"] == tclib.TC_TRIANGLE_FREE
+    _say("empty n=5")
+    r = run_gpu(tclib, e, e, 5, device=False)
+    assert r["m"] == 0 and np.all(r["tc"] == 0.0) and np.all(r["tri"] == 0)
+    _say("triangle-free path")
+    src = np.array([0, 1, 2, 3], np.int32)
+    dst = np.array([1, 2, 3, 4], np.int32)
+    r = run_gpu(tclib, src, dst, 6)
+    assert r["status"] == tclib.TC_TRIANGLE_FREE and np.all(r["tc"] == 0.0)
+    _say("only loops")
+    r = run_gpu(tclib, np.array([2, 2], np.int32), np.array([2, 2], np.int32), 3)
+    assert r["m"] == 0
+
+
+def test_errors(tclib):
+    src = np.array([0, 7], np.int32)
+    dst = np.array([1, 2], np.int32)
+    _say("vertex range host")
+    with pytest.raises(tclib.TCError) as ei:
+        tclib.Graph.from_edges(src, dst, 5)
+    assert ei.value.status == tclib.TC_ERR_VERTEX_RANGE
+    _say("vertex range device")
+    with pytest.raises(tclib.TCError) as ei:
+        tclib.Graph.from_edges(torch.as_tensor(src).cuda(), torch.as_tensor(dst).cuda(), 5)
+    assert ei.value.status == tclib.TC_ERR_VERTEX_RANGE
+    neg = np.array([-1], np.int32)
+    with pytest.raises(tclib.TCError):
+        tclib.Graph.from_edges(neg, np.array([0], np.int32), 5)
+    _say("results before compute")
+    g = tclib.Graph.from_edges(np.array([0], np.int32), np.array([1], np.int32), 2)
+    with pytest.raises(tclib.TCError) as ei:
+        g.results()
+    assert ei.value.status == tclib.TC_ERR_NOT_COMPUTED
+    with pytest.raises(tclib.TCError):
+        g.compute({"light_max_dplus": 1})
+    g.close()
+
+
+def test_top_k_ranking(tclib):
+    src, dst, n = gg.ba(5000, 5, seed=12)
+    ref = native.o2_paper(src, dst, n)
+    order = np.lexsort((np.arange(n), -ref.tc))
+    _say("top-k")
+    g = tclib.Graph.from_edges(src, dst, n)
+    g.compute()
+    verts, vals = g.top_k(50)
+    np.testing.assert_array_equal(verts, order[:50])
+    np.testing.assert_array_equal(vals.view(np.uint64), ref.tc[order[:50]].view(np.uint64))
+    verts, _ = g.top_k(n + 10)
+    np.testing.assert_array_equal(verts, order)
+    g.close()
+
+
+def test_batch_equals_single(tclib):
+    ns, ms = gg.batched_ba_sizes(40, seed=77, n_hi=3000)
+    src, dst, po, vo = gg.batched_ba(ns=ns, ms=ms, seed=77)
+    _say("batch of", len(ns))
+    g = tclib.Graph.batch(src, dst, po, vo)
+    g.compute()
+    res = g.results()
+    eu, ev = g.edges()
+    eoff = g.edge_offsets()
+    g.close()
+    for gi in range(len(ns)):
+        s, d = src[po[gi]:po[gi + 1]], dst[po[gi]:po[gi + 1]]
+        ref = native.o2_paper(s, d, int(ns[gi]), nthreads=2)
+        a, b = vo[gi], vo[gi + 1]
+        e0, e1 = eoff[gi], eoff[gi + 1]
+        np.testing.assert_array_equal(eu[e0:e1] - a, ref.eu)
+        np.testing.assert_array_equal(ev[e0:e1] - a, ref.ev)
+        np.testing.assert_array_equal(res["support"][e0:e1], ref.sup)
+        np.testing.assert_array_equal(res["tri"][a:b], ref.tri)
+        assert int(res["triG"][gi]) == ref.triG
+        np.testing.assert_array_equal(res["num"][a:b], ref.num)
+        np.testing.assert_array_equal(res["tc"][a:b].view(np.uint64), ref.tc.view(np.uint64))
