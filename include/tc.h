@@ -89,15 +89,35 @@ const char *tc_status_string(int32_t status);
  *                    a multiple of 64.
  *   light_block      workgroup size of the light-row kernel: 64..1024,
  *                    a multiple of 64 (one row per wavefront).
- *   lds_max_entries  largest per-row LDS hash table of the heavy kernel
- *                    (power of two, 1024..16384); rows needing more are
- *                    probed by binary search in device memory instead.
+ *   lds_max_entries  slots of the largest per-row LDS hash table of the
+ *                    heavy kernel (power of two, 1024..16384; a table is
+ *                    kept at most half full, so rows with more than
+ *                    lds_max_entries/2 entries are probed by binary search
+ *                    in device memory instead).
+ *   algorithm        which vertex of each triangle owns the hash table:
+ *                    TC_ALGO_LOW_PIVOT  the lowest-ordered one, v: N_H(v)
+ *                      is hashed and N_H(u) streamed for every u in N_H(v)
+ *                      (the appendix's alternative TriangleNeighbor,
+ *                      Procedure 2, intersecting N_H(v) and N_H(u));
+ *                    TC_ALGO_MID_PIVOT  the middle one, v: N_H(v) is
+ *                      hashed (Procedure 1's marking of T) and, for every
+ *                      lower neighbour u in N_L(v), only the part of N_H(u)
+ *                      above v is streamed (Procedure 1's inner loop);
+ *                    TC_ALGO_AUTO (0) picks the middle pivot, whose
+ *                    streamed work is the number of oriented wedges.
+ *                    In the middle-pivot form "rows" are the pivots v and
+ *                    the bins above are taken on |N_H(v)| of the pivot.
  * ---------------------------------------------------------------------- */
+#define TC_ALGO_AUTO 0
+#define TC_ALGO_LOW_PIVOT 1
+#define TC_ALGO_MID_PIVOT 2
+
 typedef struct tc_tuning {
     int32_t light_max_dplus;
     int32_t heavy_block;
     int32_t light_block;
     int32_t lds_max_entries;
+    int32_t algorithm;
 } tc_tuning;
 
 /* Writes the built-in defaults to *t. */
@@ -206,30 +226,36 @@ tc_status tc_top_k(const tc_graph *g, int32_t k, int32_t *vertices, double *valu
  *   (Sec. "Algorithm", Lemma 1 bounds the same sums), computed on the
  *   device from the handle's oriented graph on `stream`, stats[
  *   TC_NUM_WORK_STATS] in the order below.  The candidate sums are
- *   Σ_{v→u} |N_H(u)| over the oriented edges whose low end v falls in each
- *   bin of the last tc_compute (light / heavy / huge); merge work is
- *   Σ_{v→u} (|N_H(v)| + |N_H(u)|); wedges Σ_v C(|N_H(v)|, 2); the edge
- *   counts are the oriented edges owned by each bin's rows.
+ *   the candidates streamed by the last tc_compute's kernels in each bin
+ *   (light / heavy / huge): with the low pivot Σ_{v→u} |N_H(u)| over the
+ *   oriented edges whose low end v is in the bin, with the middle pivot
+ *   Σ |{w ∈ N_H(u) : w > v}| over the pairs u ∈ N_L(v) of the bin's pivots
+ *   v; the edge counts are the oriented edges (low pivot) or pairs (middle
+ *   pivot) of each bin.  Merge work is Σ_{v→u} (|N_H(v)| + |N_H(u)|),
+ *   wedges Σ_v C(|N_H(v)|, 2), W_hash Σ_{v→u} |N_H(u)|.
  * ---------------------------------------------------------------------- */
-#define TC_NUM_STAGES 9
+#define TC_NUM_STAGES 10
 enum {
     TC_STAGE_CSR_BUILD = 0,   /* dedup + symmetric CSR                  */
     TC_STAGE_DEGREE_RANK = 1, /* degree ordering                        */
     TC_STAGE_ORIENT = 2,      /* oriented CSR over ranks                */
-    TC_STAGE_BIN = 3,         /* row binning by |N_H(v)|                */
+    TC_STAGE_BIN = 3,         /* row binning by |N_H(v)| (+ transposed
+                                 orientation on first use, middle pivot) */
     TC_STAGE_COUNT_LIGHT = 4, /* intersection, wavefront per row        */
     TC_STAGE_COUNT_HEAVY = 5, /* intersection, workgroup per row (LDS)  */
     TC_STAGE_COUNT_HUGE = 6,  /* intersection, device-memory probe      */
-    TC_STAGE_TRI = 7,         /* support per edge, tri(v), triG         */
-    TC_STAGE_AGGREGATE = 8    /* Algorithm 2 sums + quotient            */
+    TC_STAGE_FOLD = 7,        /* bit-matrix fold (middle pivot only)    */
+    TC_STAGE_TRI = 8,         /* support per edge, tri(v), triG         */
+    TC_STAGE_AGGREGATE = 9    /* Algorithm 2 sums + quotient            */
 };
-#define TC_NUM_WORK_STATS 15
+#define TC_NUM_WORK_STATS 17
 enum {
     TC_STAT_N = 0, TC_STAT_M = 1, TC_STAT_MAX_DPLUS = 2,
     TC_STAT_ROWS_LIGHT = 3, TC_STAT_ROWS_HEAVY = 4, TC_STAT_ROWS_HUGE = 5,
     TC_STAT_CAND_LIGHT = 6, TC_STAT_CAND_HEAVY = 7, TC_STAT_CAND_HUGE = 8,
     TC_STAT_MERGE_WORK = 9, TC_STAT_WEDGES = 10, TC_STAT_TRIANGLES = 11,
-    TC_STAT_EDGES_LIGHT = 12, TC_STAT_EDGES_HEAVY = 13, TC_STAT_EDGES_HUGE = 14
+    TC_STAT_EDGES_LIGHT = 12, TC_STAT_EDGES_HEAVY = 13, TC_STAT_EDGES_HUGE = 14,
+    TC_STAT_W_HASH = 15, TC_STAT_ALGORITHM = 16
 };
 
 tc_status tc_set_profiling(int32_t on);

@@ -26,6 +26,7 @@ HIP_SOURCES = [
     "tc_scan.hip",
     "tc_build.hip",
     "tc_count.hip",
+    "tc_count_mid.hip",
     "tc_aggregate.hip",
     "tc_api.hip",
 ]

@@ -229,8 +229,8 @@ tc_status tc_aggregate(tc_graph *g, hipStream_t s) {
     const int64_t *voff = G > 1 ? g->vtx_off : nullptr;
     TC_HIP(hipMemsetAsync(g->triG, 0, sizeof(uint64_t) * G, s));
     if (n == 0) {
-        tc_prof_mark(g, 9, s);
         tc_prof_mark(g, 10, s);
+        tc_prof_mark(g, 11, s);
         return TC_OK;
     }
 
@@ -266,7 +266,7 @@ tc_status tc_aggregate(tc_graph *g, hipStream_t s) {
     TC_LAUNCHED();
     k_tri_finish<<<grid_for(G), BK, 0, s>>>(G, g->triG, g->err);
     TC_LAUNCHED();
-    tc_prof_mark(g, 9, s);
+    tc_prof_mark(g, 10, s);
     k_num_small<<<small_grid, BK, 0, s>>>(n, g->row_ptr, g->col, g->flag, g->tri, g->triG, voff, G,
                                           g->num, g->tcv);
     TC_LAUNCHED();
@@ -275,6 +275,6 @@ tc_status tc_aggregate(tc_graph *g, hipStream_t s) {
             big, nbig, g->row_ptr, g->col, g->flag, g->tri, g->triG, voff, G, g->num, g->tcv);
         TC_LAUNCHED();
     }
-    tc_prof_mark(g, 10, s);
+    tc_prof_mark(g, 11, s);
     return TC_OK;
 }

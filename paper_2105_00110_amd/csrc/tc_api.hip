@@ -29,7 +29,7 @@ void tc_prof_mark(tc_graph *g, int idx, hipStream_t s) {
     }
     (void)hipEventRecord(g->prof_ev[idx], s);
     if (idx == 3) g->prof_build = true;
-    if (idx == 10) g->prof_compute = true;
+    if (idx == 11) g->prof_compute = true;
 }
 
 static std::mutex g_pool_mu;
@@ -149,7 +149,8 @@ tc_status copy_out(void *dst, const void *src, size_t bytes, int32_t mem_kind, h
 void free_graph_arrays(tc_graph *g, hipStream_t s) {
     void *arrs[] = {g->eu,   g->ev,   g->row_ptr, g->col,  g->sym2e, g->rank, g->perm,
                     g->orp,  g->ocol, g->o2e,     g->osup, g->esup,  g->flag, g->tri,
-                    g->num,  g->tcv,  g->triG,    g->vtx_off, g->err, g->bin_rows};
+                    g->num,  g->tcv,  g->triG,    g->vtx_off, g->err, g->bin_rows,
+                    g->in_ptr, g->in_pair, g->rowbase, g->hitbits};
     for (void *p : arrs) tc_dev_free(p, s);
 }
 
@@ -503,8 +504,8 @@ tc_status tc_set_profiling(int32_t on) {
 tc_status tc_get_stage_ms(const tc_graph *g, double *ms) {
     if (!g || !ms) return TC_ERR_INVALID_ARG;
     if (!g->prof_build && !g->prof_compute) return TC_ERR_NOT_COMPUTED;
-    static const int from[TC_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7, 8, 9};
-    static const int to[TC_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8, 9, 10};
+    static const int from[TC_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7, 8, 9, 10};
+    static const int to[TC_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8, 9, 10, 11};
     for (int i = 0; i < TC_NUM_STAGES; ++i) {
         ms[i] = 0.0;
         bool build = to[i] <= 3;

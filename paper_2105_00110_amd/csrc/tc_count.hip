@@ -25,11 +25,13 @@
 // LDS budget) probe by binary search in device memory.  The schedule never
 // changes a result: every count is an integer sum.
 #include "tc_internal.h"
+#include "tc_table.h"
 
 namespace {
 
-constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 constexpr int BK = 256;
+constexpr int UNROLL = 4;  // independent candidate loads in flight per lane
+using namespace tc_tab;
 
 static inline unsigned grid_for(int64_t n, int block = BK) {
     int64_t g = tc_div_up(n, block);
@@ -38,188 +40,166 @@ static inline unsigned grid_for(int64_t n, int block = BK) {
     return (unsigned)g;
 }
 
-static inline int ceil_log2(int64_t x) {
-    int b = 0;
-    while ((1ll << b) < x) ++b;
-    return b;
-}
-
-__device__ __forceinline__ int ceil_log2_dev(int x) {
-    return x <= 1 ? 0 : 32 - __clz(x - 1);
-}
-
-__device__ __forceinline__ uint32_t hash_slot(uint32_t key, int cb) {
-    return (key * 0x9E3779B1u) >> (32 - cb);
-}
-
-__device__ __forceinline__ void hash_insert(uint32_t *hkey, uint32_t *hpos, int cb, uint32_t key,
-                                            uint32_t pos) {
-    const uint32_t mask = (1u << cb) - 1;
-    uint32_t h = hash_slot(key, cb);
-    while (true) {
-        uint32_t prev = atomicCAS(&hkey[h], EMPTY, key);
-        if (prev == EMPTY) {
-            hpos[h] = pos;
-            return;
-        }
-        h = (h + 1) & mask;
-    }
-}
-
-__device__ __forceinline__ int hash_find(const uint32_t *hkey, const uint32_t *hpos, int cb,
-                                         uint32_t key) {
-    const uint32_t mask = (1u << cb) - 1;
-    uint32_t h = hash_slot(key, cb);
-    while (true) {
-        uint32_t k = hkey[h];
-        if (k == key) return (int)hpos[h];
-        if (k == EMPTY) return -1;
-        h = (h + 1) & mask;
-    }
-}
-
-// Streams N_H(u) = ocol[ub, ue) against the table of row v and applies the
-// support updates.  Returns |N_H(v) ∩ N_H(u)| (wave-uniform).
+// Streams N_H(u) = ocol[ub, ue) against row v and applies the support
+// updates; returns |N_H(v) ∩ N_H(u)| (wave-uniform).  Each lane keeps
+// UNROLL loads in flight; the stream stops once it passes vmax = max N_H(v).
 template <bool GLOBAL_LOOKUP>
 __device__ __forceinline__ uint32_t stream_u(const int32_t *__restrict__ ocol, int64_t ub,
-                                             int64_t ue, uint32_t vmax, const uint32_t *hkey,
-                                             const uint32_t *hpos, int cb, uint32_t *lsup,
-                                             int64_t vstart, int dv, uint32_t *__restrict__ osup) {
+                                             int64_t ue, uint32_t vmax, const RowTable &t,
+                                             uint32_t *lsup, int64_t vstart, int dv,
+                                             uint32_t *__restrict__ osup) {
     const int lane = __lane_id();
     uint32_t c = 0;
-    for (int64_t jb = ub; jb < ue; jb += TC_WAVE) {
-        int64_t j = jb + lane;
-        bool in = j < ue;
-        uint32_t w = in ? (uint32_t)ocol[j] : EMPTY;
-        if ((uint32_t)__shfl(w, 0, TC_WAVE) > vmax) break;
-        int p = -1;
-        if (in && w <= vmax) {
-            if constexpr (GLOBAL_LOOKUP) {
-                int lo = 0, hi = dv;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if ((uint32_t)ocol[vstart + mid] < w) lo = mid + 1; else hi = mid;
-                }
-                if (lo < dv && (uint32_t)ocol[vstart + lo] == w) p = lo;
-            } else {
-                p = hash_find(hkey, hpos, cb, w);
+    for (int64_t jb = ub; jb < ue; jb += TC_WAVE * UNROLL) {
+        uint32_t w[UNROLL];
+#pragma unroll
+        for (int q = 0; q < UNROLL; ++q) {
+            const int64_t j = jb + q * TC_WAVE + lane;
+            w[q] = j < ue ? (uint32_t)ocol[j] : EMPTY;
+        }
+        // lane 0's first load is the smallest candidate of the chunk
+        if ((uint32_t)__shfl(w[0], 0, TC_WAVE) > vmax) break;
+        // EMPTY (past the row end) is above every rank: never looked up
+        int pq[UNROLL];
+        if constexpr (GLOBAL_LOOKUP) {
+#pragma unroll
+            for (int q = 0; q < UNROLL; ++q)
+                pq[q] = w[q] <= vmax ? row_search(ocol, vstart, dv, w[q]) : -1;
+        } else {
+            table_find_n<UNROLL>(t, w, vmax, pq);
+        }
+#pragma unroll
+        for (int q = 0; q < UNROLL; ++q) {
+            const int p = pq[q];
+            const bool hit = p >= 0;
+            if (hit) {
+                if constexpr (GLOBAL_LOOKUP) atomicAdd(&osup[vstart + p], 1u);
+                else atomicAdd(&lsup[p], 1u);
+                atomicAdd(&osup[jb + q * TC_WAVE + lane], 1u);
             }
+            c += (uint32_t)__popcll(__ballot(hit));
         }
-        bool hit = p >= 0;
-        if (hit) {
-            if constexpr (GLOBAL_LOOKUP) atomicAdd(&osup[vstart + p], 1u);
-            else atomicAdd(&lsup[p], 1u);
-            atomicAdd(&osup[j], 1u);
-        }
-        c += (uint32_t)__popcll(__ballot(hit));
+        if ((uint32_t)__shfl(w[UNROLL - 1], TC_WAVE - 1, TC_WAVE) > vmax) break;
     }
     return c;
 }
 
-// One wavefront per light row.  LDS per wavefront: table (2·cap words) and
-// the row's support counters (dcap words).
+// Per-wave LDS footprint of the light kernel (bytes, 16-aligned).
+__host__ __device__ __forceinline__ size_t light_wave_bytes(int dcap) {
+    const size_t nb = (size_t)1 << bucket_bits(dcap);
+    return (16 * nb + 2 * 4 * nb + 4 * (size_t)dcap + 15) & ~(size_t)15;
+}
+
+// One wavefront per light row.
 __global__ __launch_bounds__(1024) void k_count_light(const int64_t *__restrict__ orp,
                                                       const int32_t *__restrict__ ocol,
                                                       const int32_t *__restrict__ rows,
-                                                      int64_t nrows, int cbmax, int dcap,
+                                                      int64_t nrows, int dcap,
                                                       uint32_t *__restrict__ osup,
                                                       unsigned long long *__restrict__ tri_total) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ uint4 lds4[];
     const int wpb = blockDim.x / TC_WAVE;
     const int wv = threadIdx.x / TC_WAVE;
     const int lane = __lane_id();
-    const int capmax = 1 << cbmax;
-    uint32_t *hkey = lds + wv * (2 * capmax + dcap);
-    uint32_t *hpos = hkey + capmax;
-    uint32_t *lsup = hpos + capmax;
+    const int nbmax = 1 << bucket_bits(dcap);
+    char *base = reinterpret_cast<char *>(lds4) + (size_t)wv * light_wave_bytes(dcap);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(base);
+    uint16_t *pos = reinterpret_cast<uint16_t *>(base + 16 * (size_t)nbmax);
+    uint32_t *lsup = reinterpret_cast<uint32_t *>(base + 24 * (size_t)nbmax);
     unsigned long long found = 0;
     for (int64_t ri = (int64_t)blockIdx.x * wpb + wv; ri < nrows; ri += (int64_t)gridDim.x * wpb) {
         const int32_t r = rows[ri];
         const int64_t start = orp[r];
         const int d = (int)(orp[r + 1] - start);
-        int cb = ceil_log2_dev(2 * d);
-        if (cb < 1) cb = 1;
-        const int cap = 1 << cb;
-        for (int j = lane; j < cap; j += TC_WAVE) hkey[j] = EMPTY;
+        const RowTable t{keys, pos, bucket_bits(d)};
+        for (int j = lane; j < (4 << t.bb); j += TC_WAVE) keys[j] = EMPTY;
         for (int j = lane; j < d; j += TC_WAVE) lsup[j] = 0;
-        for (int j = lane; j < d; j += TC_WAVE) hash_insert(hkey, hpos, cb, (uint32_t)ocol[start + j], j);
+        for (int j = lane; j < d; j += TC_WAVE) table_insert(t, (uint32_t)ocol[start + j], j);
         const uint32_t vmax = (uint32_t)ocol[start + d - 1];
         for (int i0 = 0; i0 < d - 1; i0 += TC_WAVE) {
             const int ii = i0 + lane;
             int64_t ub_l = 0, ue_l = 0;
             if (ii < d - 1) {
-                int32_t u = ocol[start + ii];
+                const int32_t u = ocol[start + ii];
                 ub_l = orp[u];
                 ue_l = orp[u + 1];
             }
             const int cnt = min(TC_WAVE, d - 1 - i0);
             for (int k = 0; k < cnt; ++k) {
-                int64_t ub = __shfl(ub_l, k, TC_WAVE), ue = __shfl(ue_l, k, TC_WAVE);
-                uint32_t c = stream_u<false>(ocol, ub, ue, vmax, hkey, hpos, cb, lsup, start, d, osup);
+                const int64_t ub = __shfl(ub_l, k, TC_WAVE), ue = __shfl(ue_l, k, TC_WAVE);
+                const uint32_t c = stream_u<false>(ocol, ub, ue, vmax, t, lsup, start, d, osup);
                 if (c != 0 && lane == 0) atomicAdd(&lsup[i0 + k], c);
                 found += c;
             }
         }
         for (int j = lane; j < d; j += TC_WAVE) {
-            uint32_t x = lsup[j];
+            const uint32_t x = lsup[j];
             if (x) atomicAdd(&osup[start + j], x);
         }
     }
     if (lane == 0 && found) atomicAdd(tri_total, found);
 }
 
-// One workgroup per heavy row; the workgroup's wavefronts share the table
-// and take the row's u in chunks of 64.  Rows are taken from the end of
-// the list (highest rank, typically the most work) first.
+// LDS footprint of the heavy kernel for rows of at most dmax entries.
+static inline size_t heavy_bytes(int dmax) {
+    const size_t nb = (size_t)1 << bucket_bits(dmax);
+    return 16 * nb + 8 * nb + 4 * (size_t)dmax;
+}
+
+// One workgroup per heavy row (GLOBAL_LOOKUP: no table, binary search in
+// device memory, for rows whose table would not fit).  Wavefront wv takes
+// the row's u at indices wv, wv + wpb, wv + 2·wpb, ...; rows are taken from
+// the end of the list (highest rank, typically the most work) first.
 template <bool GLOBAL_LOOKUP>
 __global__ __launch_bounds__(1024) void k_count_heavy(const int64_t *__restrict__ orp,
                                                       const int32_t *__restrict__ ocol,
                                                       const int32_t *__restrict__ rows,
-                                                      int64_t nrows, int cbmax, int dcap,
+                                                      int64_t nrows, int dmax,
                                                       uint32_t *__restrict__ osup,
                                                       unsigned long long *__restrict__ tri_total) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ uint4 lds4[];
     const int wpb = blockDim.x / TC_WAVE;
     const int wv = threadIdx.x / TC_WAVE;
     const int lane = __lane_id();
-    const int capmax = GLOBAL_LOOKUP ? 0 : (1 << cbmax);
-    uint32_t *hkey = lds;
-    uint32_t *hpos = hkey + capmax;
-    uint32_t *lsup = hpos + capmax;
+    const int nbmax = GLOBAL_LOOKUP ? 0 : (1 << bucket_bits(dmax));
+    char *base = reinterpret_cast<char *>(lds4);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(base);
+    uint16_t *pos = reinterpret_cast<uint16_t *>(base + 16 * (size_t)nbmax);
+    uint32_t *lsup = reinterpret_cast<uint32_t *>(base + 24 * (size_t)nbmax);
     unsigned long long found = 0;
     for (int64_t bi = blockIdx.x; bi < nrows; bi += gridDim.x) {
         const int32_t r = rows[nrows - 1 - bi];
         const int64_t start = orp[r];
         const int d = (int)(orp[r + 1] - start);
-        int cb = 1;
+        RowTable t{keys, pos, 0};
         if constexpr (!GLOBAL_LOOKUP) {
-            cb = ceil_log2_dev(2 * d);
-            if (cb < 1) cb = 1;
-            const int cap = 1 << cb;
-            for (int j = threadIdx.x; j < cap; j += blockDim.x) hkey[j] = EMPTY;
+            t.bb = bucket_bits(d);
+            for (int j = threadIdx.x; j < (4 << t.bb); j += blockDim.x) keys[j] = EMPTY;
             for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
             __syncthreads();
             for (int j = threadIdx.x; j < d; j += blockDim.x)
-                hash_insert(hkey, hpos, cb, (uint32_t)ocol[start + j], j);
+                table_insert(t, (uint32_t)ocol[start + j], j);
             __syncthreads();
         }
         const uint32_t vmax = (uint32_t)ocol[start + d - 1];
-        for (int i0 = wv * TC_WAVE; i0 < d - 1; i0 += wpb * TC_WAVE) {
-            const int ii = i0 + lane;
+        const int nu = d - 1;  // the last entry closes no triangle in this row
+        for (int k0 = 0; wv + wpb * k0 < nu; k0 += TC_WAVE) {
+            const int ii = wv + wpb * (k0 + lane);
             int64_t ub_l = 0, ue_l = 0;
-            if (ii < d - 1) {
-                int32_t u = ocol[start + ii];
+            if (ii < nu) {
+                const int32_t u = ocol[start + ii];
                 ub_l = orp[u];
                 ue_l = orp[u + 1];
             }
-            const int cnt = min(TC_WAVE, d - 1 - i0);
-            for (int k = 0; k < cnt; ++k) {
-                int64_t ub = __shfl(ub_l, k, TC_WAVE), ue = __shfl(ue_l, k, TC_WAVE);
-                uint32_t c = stream_u<GLOBAL_LOOKUP>(ocol, ub, ue, vmax, hkey, hpos, cb, lsup, start,
-                                                     d, osup);
+            for (int k = 0; k < TC_WAVE; ++k) {
+                const int i = wv + wpb * (k0 + k);
+                if (i >= nu) break;
+                const int64_t ub = __shfl(ub_l, k, TC_WAVE), ue = __shfl(ue_l, k, TC_WAVE);
+                const uint32_t c =
+                    stream_u<GLOBAL_LOOKUP>(ocol, ub, ue, vmax, t, lsup, start, d, osup);
                 if (c != 0 && lane == 0) {
-                    if constexpr (GLOBAL_LOOKUP) atomicAdd(&osup[start + i0 + k], c);
-                    else atomicAdd(&lsup[i0 + k], c);
+                    if constexpr (GLOBAL_LOOKUP) atomicAdd(&osup[start + i], c);
+                    else atomicAdd(&lsup[i], c);
                 }
                 found += c;
             }
@@ -227,13 +207,12 @@ __global__ __launch_bounds__(1024) void k_count_heavy(const int64_t *__restrict_
         if constexpr (!GLOBAL_LOOKUP) {
             __syncthreads();
             for (int j = threadIdx.x; j < d; j += blockDim.x) {
-                uint32_t x = lsup[j];
+                const uint32_t x = lsup[j];
                 if (x) atomicAdd(&osup[start + j], x);
             }
             __syncthreads();
         }
     }
-    (void)dcap;
     if (lane == 0 && found) atomicAdd(tri_total, found);
 }
 
@@ -252,15 +231,6 @@ __global__ void k_bin_write(int32_t n, const int64_t *__restrict__ orp, int lo, 
          r += (int64_t)gridDim.x * blockDim.x) {
         int64_t d = orp[r + 1] - orp[r];
         if (d >= lo && d <= hi) out[pos[r]] = (int32_t)r;
-    }
-}
-
-__global__ void k_max_in_list(const int64_t *__restrict__ orp, const int32_t *__restrict__ rows,
-                              int64_t nrows, uint32_t *__restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrows;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int32_t r = rows[i];
-        atomicMax(out, (uint32_t)(orp[r + 1] - orp[r]));
     }
 }
 
@@ -291,6 +261,7 @@ tc_status tc_tuning_default(tc_tuning *t) {
     t->heavy_block = 256;
     t->light_block = 256;
     t->lds_max_entries = 4096;
+    t->algorithm = TC_ALGO_AUTO;
     return TC_OK;
 }
 
@@ -299,7 +270,8 @@ static bool tuning_valid(const tc_tuning *t) {
     return t->light_max_dplus >= 2 && t->light_max_dplus <= 1024 && t->heavy_block >= 64 &&
            t->heavy_block <= 1024 && t->heavy_block % 64 == 0 && t->light_block >= 64 &&
            t->light_block <= 1024 && t->light_block % 64 == 0 && pow2(t->lds_max_entries) &&
-           t->lds_max_entries >= 1024 && t->lds_max_entries <= 16384;
+           t->lds_max_entries >= 1024 && t->lds_max_entries <= 16384 && t->algorithm >= 0 &&
+           t->algorithm <= 2;
 }
 
 tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
@@ -317,18 +289,20 @@ tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
         g->n_light = g->n_heavy = g->n_huge = 0;
         g->light_max = t.light_max_dplus;
         g->huge_min = 0x7FFFFFFF;
-        for (int k = 5; k <= 8; ++k) tc_prof_mark(g, k, s);
+        for (int k = 5; k <= 9; ++k) tc_prof_mark(g, k, s);
         return TC_OK;
     }
 
-    // The heavy kernel needs 8 bytes per table entry plus 4 per row entry
-    // (at most half the table) in LDS: clamp the table to what one
-    // workgroup may allocate on this device.
+    // The heavy kernel's table and counters must fit one workgroup's LDS:
+    // clamp the table size to what this device allows.
     int dev = 0, lds_limit = 65536;
     TC_HIP(hipGetDevice(&dev));
     TC_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     int max_entries = t.lds_max_entries;
-    while (max_entries > 1024 && (size_t)max_entries * 10 > (size_t)lds_limit) max_entries >>= 1;
+    while (max_entries > 1024 && heavy_bytes(max_entries / 2) > (size_t)lds_limit) max_entries >>= 1;
+    const int algo = t.algorithm == TC_ALGO_LOW_PIVOT ? TC_ALGO_LOW_PIVOT : TC_ALGO_MID_PIVOT;
+    g->algo_used = algo;
+    if (algo == TC_ALGO_MID_PIVOT) return tc_count_mid(g, t, lds_limit, max_entries, found, s);
     const int light_max = t.light_max_dplus;
     // heavy rows: light_max < d+ < huge_min (table at most half full); the
     // three bins must not overlap, whatever the knobs
@@ -352,44 +326,36 @@ tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
 
     if (nl > 0) {
         const int dcap = light_max;
-        const int cbmax = ceil_log2(2 * (int64_t)light_max);
-        const size_t per_wave = (2 * ((size_t)1 << cbmax) + dcap) * sizeof(uint32_t);
+        const size_t per_wave = light_wave_bytes(dcap);
         int wpb = t.light_block / TC_WAVE;
         while (wpb > 1 && (size_t)wpb * per_wave > (size_t)lds_limit) --wpb;
         const int block = wpb * TC_WAVE;
         const size_t lds = (size_t)wpb * per_wave;
         int64_t blocks = tc_div_up(nl, wpb);
         if (blocks > 65536) blocks = 65536;
-        k_count_light<<<(unsigned)blocks, block, lds, s>>>(g->orp, g->ocol, rows, nl, cbmax, dcap,
-                                                         g->osup, found);
+        k_count_light<<<(unsigned)blocks, block, lds, s>>>(g->orp, g->ocol, rows, nl, dcap, g->osup,
+                                                         found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 6, s);
     if (nh > 0) {
-        uint32_t *dmax = nullptr;
-        TC_TRY(tmp.get(&dmax, 1));
-        TC_HIP(hipMemsetAsync(dmax, 0, 4, s));
-        k_max_in_list<<<grid_for(nh), BK, 0, s>>>(g->orp, heavy, nh, dmax);
-        TC_LAUNCHED();
-        uint32_t hmax = 0;
-        TC_HIP(hipMemcpyAsync(&hmax, dmax, 4, hipMemcpyDeviceToHost, s));
-        TC_HIP(hipStreamSynchronize(s));
-        const int cbmax = ceil_log2(2 * (int64_t)hmax);
-        const size_t lds = (2 * ((size_t)1 << cbmax) + hmax) * sizeof(uint32_t);
+        // every heavy row has light_max < d+ < huge_min and d+ <= max d+
+        const int hmax = g->max_dplus < huge_min - 1 ? g->max_dplus : huge_min - 1;
+        const size_t lds = heavy_bytes(hmax);
         int64_t blocks = nh < 1048576 ? nh : 1048576;
-        tc_prof_mark(g, 6, s);  // after the host round trip for the table size
         k_count_heavy<false><<<(unsigned)blocks, t.heavy_block, lds, s>>>(
-            g->orp, g->ocol, heavy, nh, cbmax, (int)hmax, g->osup, found);
+            g->orp, g->ocol, heavy, nh, hmax, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 7, s);
     if (nz > 0) {
         int64_t blocks = nz < 65536 ? nz : 65536;
         k_count_heavy<true><<<(unsigned)blocks, t.heavy_block, 0, s>>>(g->orp, g->ocol, huge, nz, 0,
-                                                                      0, g->osup, found);
+                                                                      g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 8, s);
+    tc_prof_mark(g, 9, s);  // the low-pivot form has no fold step
     return TC_OK;
 }
 
@@ -400,7 +366,7 @@ namespace {
 
 __global__ void k_work_stats(int32_t n, const int64_t *__restrict__ orp,
                              const int32_t *__restrict__ ocol, int light_max, int huge_min,
-                             unsigned long long *__restrict__ acc) {
+                             bool low_bins, unsigned long long *__restrict__ acc) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = orp[r], e = orp[r + 1];
@@ -414,13 +380,14 @@ __global__ void k_work_stats(int32_t n, const int64_t *__restrict__ orp,
             merge += d + du;
         }
         int bin = d < 2 ? -1 : (d <= light_max ? 0 : (d < huge_min ? 1 : 2));
-        if (bin >= 0) {
+        if (bin >= 0 && low_bins) {
             atomicAdd(&acc[bin], 1ull);
             atomicAdd(&acc[3 + bin], cand);
             atomicAdd(&acc[8 + bin], (unsigned long long)d);
         }
         atomicAdd(&acc[6], merge);
         atomicAdd(&acc[7], (unsigned long long)(d * (d - 1) / 2));
+        atomicAdd(&acc[11], cand);
     }
 }
 
@@ -434,13 +401,16 @@ tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s) {
     if (g->n == 0 || g->m == 0) return TC_OK;
     tc_scratch tmp(s);
     unsigned long long *acc = nullptr;
-    TC_TRY(tmp.get(&acc, 11));
-    TC_HIP(hipMemsetAsync(acc, 0, 11 * sizeof(unsigned long long), s));
+    TC_TRY(tmp.get(&acc, 12));
+    TC_HIP(hipMemsetAsync(acc, 0, 12 * sizeof(unsigned long long), s));
     int light_max = g->light_max > 0 ? g->light_max : 64;
     int huge_min = g->huge_min > 0 ? g->huge_min : 0x7FFFFFFF;
-    k_work_stats<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, g->ocol, light_max, huge_min, acc);
+    const bool mid = g->algo_used != TC_ALGO_LOW_PIVOT;
+    k_work_stats<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, g->ocol, light_max, huge_min, !mid,
+                                               acc);
     TC_LAUNCHED();
-    unsigned long long h[11];
+    if (mid) TC_TRY(tc_mid_stats(g, acc, s));
+    unsigned long long h[12];
     uint64_t tri = 0;
     TC_HIP(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
     if (g->triG) TC_HIP(hipMemcpyAsync(&tri, g->triG + g->num_graphs, 8, hipMemcpyDeviceToHost, s));
@@ -457,5 +427,7 @@ tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s) {
     stats[TC_STAT_EDGES_LIGHT] = (int64_t)h[8];
     stats[TC_STAT_EDGES_HEAVY] = (int64_t)h[9];
     stats[TC_STAT_EDGES_HUGE] = (int64_t)h[10];
+    stats[TC_STAT_W_HASH] = (int64_t)h[11];
+    stats[TC_STAT_ALGORITHM] = mid ? TC_ALGO_MID_PIVOT : TC_ALGO_LOW_PIVOT;
     return TC_OK;
 }

@@ -1,0 +1,661 @@
+// Triangle counting with per-edge support, middle-pivot form.
+//
+// This is the paper's Procedure 1 (TriangleNeighbor, Sec. "Algorithm") on
+// the degree-ordered orientation: for a pivot v, mark N_H(v) (the array T
+// of the procedure, here an LDS hash table); for every lower neighbour u of
+// v (u ∈ N_L(v)) scan N_H(u) for marked entries.  Reading the procedure's
+// test as "T(w) is 1" for w ∈ N_H(u), each hit w is a triangle u < v < w
+// (u low, v middle, w high), found exactly once.  Since w must lie above v
+// in N_H(u) (which is sorted), only the part of N_H(u) after v's own slot is
+// scanned: the streamed work is Σ_u C(|N_H(u)|, 2), the number of oriented
+// wedges, instead of Σ_{v→u} |N_H(u)| for the low-pivot form.
+//
+// Support updates per triangle (u, v, w):
+//   sup(v,w) += 1   LDS counter of the pivot's slot, flushed once per slot;
+//   sup(u,v), sup(u,w): both lie in u's row.  Every scanned pair (u, v)
+//   records its hits as a bit row over u's tail after v (bit b <-> the
+//   entry b+1 places after v's slot), written with plain 32-bit stores; u's
+//   rows form a triangular bit matrix B_u (row i = pair (u, N_H(u)[i])).
+//   A second kernel folds each B_u: the popcount of row i is the number of
+//   triangles on (u, N_H(u)[i]) as its (low, middle) edge, the sum of
+//   column j is the number on (u, N_H(u)[j]) as its (low, high) edge.  So no
+//   support update of the scan goes to device memory by atomic.
+//
+// Data: the transposed orientation in_pair, grouped by pivot: entry i of
+// pivot v holds (u << 32) | k where k is the slot of v in N_H(u); the scan
+// runs over ocol[k+1, orp[u+1]).  B_u starts at word rowbase[u]; its row i
+// holds ceil((d-1-i)/32) words (d = |N_H(u)|), so row i starts at word
+// S(d) - S(d-i) with S(d) = Σ_{t<d} ceil(t/32).
+//
+// Work mapping.  A work item is a pivot with a slice of its pairs.  A
+// wavefront takes 64 pairs at a time and flattens their bit rows: a prefix
+// sum of the row lengths in words places word x of the group, and the lane
+// that owns word x scans its 32 candidates and stores the word, so short
+// and long scans both keep all 64 lanes busy.  Pivots with small |N_H(v)|
+// are one wavefront per item with a private table; larger ones share a
+// workgroup table; pivots whose table does not fit LDS probe N_H(v) by
+// binary search in device memory.
+#include "tc_internal.h"
+#include "tc_table.h"
+
+namespace {
+
+using namespace tc_tab;
+
+constexpr int BK = 256;
+constexpr int WAVE_ITEM_PAIRS = 256;  // pairs per wavefront item
+constexpr int BLOCK_ITEM_GROUPS = 4;  // 64-pair groups per wavefront in a workgroup item
+constexpr size_t GROUP_BYTES = 64 * 8 * 3 + 64 * 4;  // gx, gs, gb (int64), gt (int32)
+
+// Words of the bit rows of a row with d entries: Σ_{t=1}^{d-1} ceil(t/32).
+__host__ __device__ __forceinline__ int64_t bit_words(int64_t d) {
+    if (d < 2) return 0;
+    const int64_t q = (d - 1) >> 5, r = (d - 1) & 31;
+    return 32 * (q * (q + 1) / 2) + (q + 1) * r;
+}
+
+static inline unsigned grid_for(int64_t n, int block = BK) {
+    int64_t g = tc_div_up(n, block);
+    if (g < 1) g = 1;
+    if (g > 0x7FFFFFFF) g = 0x7FFFFFFF;
+    return (unsigned)g;
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// ---------------------------------------------------------------------------
+// Transposed orientation
+// ---------------------------------------------------------------------------
+__global__ void k_slot_rows(int32_t n, const int64_t *__restrict__ orp, uint32_t *__restrict__ key,
+                            uint64_t *__restrict__ val, const int32_t *__restrict__ ocol) {
+    GRID_STRIDE(r, n) {
+        for (int64_t k = orp[r]; k < orp[r + 1]; ++k) {
+            key[k] = (uint32_t)ocol[k];
+            val[k] = ((uint64_t)(uint32_t)r << 32) | (uint64_t)k;
+        }
+    }
+}
+
+__global__ void k_in_runs(const uint32_t *__restrict__ key, int64_t len, uint32_t *__restrict__ start,
+                          uint32_t *__restrict__ end) {
+    GRID_STRIDE(i, len) {
+        const uint32_t x = key[i];
+        if (i == 0 || key[i - 1] != x) start[x] = (uint32_t)i;
+        if (i == len - 1 || key[i + 1] != x) end[x] = (uint32_t)(i + 1);
+    }
+}
+
+__global__ void k_in_len(int32_t n, const uint32_t *__restrict__ s, const uint32_t *__restrict__ e,
+                         int64_t *__restrict__ len) {
+    GRID_STRIDE(x, n) len[x] = e[x] - s[x];
+}
+
+// ---------------------------------------------------------------------------
+// Work items: pivot v with |N_H(v)| in [lo, hi] and at least one lower
+// neighbour, cut into slices of at most S pairs.
+// ---------------------------------------------------------------------------
+__global__ void k_item_count(int32_t n, const int64_t *__restrict__ orp,
+                             const int64_t *__restrict__ in_ptr, int lo, int hi, int S,
+                             uint32_t *__restrict__ cnt) {
+    GRID_STRIDE(v, n) {
+        const int64_t d = orp[v + 1] - orp[v];
+        const int64_t in = in_ptr[v + 1] - in_ptr[v];
+        cnt[v] = (d >= lo && d <= hi && in > 0) ? (uint32_t)tc_div_up(in, S) : 0u;
+    }
+}
+
+__global__ void k_item_write(int32_t n, const uint32_t *__restrict__ cnt,
+                             const uint32_t *__restrict__ off, const int64_t *__restrict__ in_ptr,
+                             int S, int32_t *__restrict__ item_v, uint32_t *__restrict__ item_first) {
+    GRID_STRIDE(v, n) {
+        const uint32_t c = cnt[v];
+        for (uint32_t t = 0; t < c; ++t) {
+            item_v[off[v] + t] = (int32_t)v;
+            item_first[off[v] + t] = (uint32_t)(in_ptr[v] + (int64_t)t * S);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One 64-pair group of pivot v (wave-level).  Pairs g0 .. gend-1 (at most
+// 64).  gx/gs/gb/gt: this wavefront's LDS arrays (exclusive scan of word
+// counts, scan starts, bit-row bases, tail lengths).
+// ---------------------------------------------------------------------------
+template <bool GLOBAL_LOOKUP>
+__device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
+                                          const int32_t *__restrict__ ocol,
+                                          const uint64_t *__restrict__ in_pair,
+                                          const int64_t *__restrict__ rowbase, int64_t g0,
+                                          int64_t gend, const RowTable &t, uint32_t hmax,
+                                          uint32_t *lsup, int64_t vstart, int dv, int64_t *gx,
+                                          int64_t *gs, int64_t *gb, int32_t *gt,
+                                          uint32_t *__restrict__ bits, uint32_t *__restrict__ osup,
+                                          unsigned long long &found) {
+    const int lane = __lane_id();
+    const int64_t i = g0 + lane;
+    int64_t words = 0;
+    if (i < gend) {
+        const uint64_t pr = in_pair[i];
+        const int64_t k = (int64_t)(uint32_t)pr;
+        const int32_t u = (int32_t)(pr >> 32);
+        const int64_t rs = orp[u];
+        const int64_t d = orp[u + 1] - rs;
+        const int64_t ii = k - rs;
+        const int64_t tail = d - 1 - ii;
+        words = (tail + 31) >> 5;
+        gs[lane] = k + 1;
+        gb[lane] = rowbase[u] + bit_words(d) - bit_words(d - ii);
+        gt[lane] = (int32_t)tail;
+    }
+    const int64_t incl = tc_wave_incl_scan(words);
+    const int64_t total = __shfl(incl, TC_WAVE - 1, TC_WAVE);
+    gx[lane] = incl - words;
+    for (int64_t base = 0; base < total; base += TC_WAVE) {
+        const int64_t x = base + lane;
+        if (x < total) {
+            int lo = 0, hi = TC_WAVE - 1;  // last pair p with gx[p] <= x
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (gx[mid] <= x) lo = mid; else hi = mid - 1;
+            }
+            const int p = lo;
+            const int64_t kw = x - gx[p];
+            const int64_t c0 = gs[p] + 32 * kw;
+            const int cnt = min(32, gt[p] - 32 * (int)kw);
+            uint32_t ww[32];
+#pragma unroll
+            for (int b = 0; b < 32; ++b) ww[b] = b < cnt ? (uint32_t)ocol[c0 + b] : EMPTY;
+            // probe in batches of 8 (EMPTY, past the tail, is above every
+            // rank and is never looked up); apply each batch's hits at once
+            uint32_t mask = 0;
+#pragma unroll
+            for (int c = 0; c < 32; c += 8) {
+                uint32_t kk[8];
+                int qc[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) kk[e] = ww[c + e];
+                if constexpr (GLOBAL_LOOKUP) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        qc[e] = kk[e] <= hmax ? row_search(ocol, vstart, dv, kk[e]) : -1;
+                } else {
+                    table_find_n<8>(t, kk, hmax, qc);
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if (qc[e] >= 0) {
+                        mask |= 1u << (c + e);
+                        if constexpr (GLOBAL_LOOKUP) atomicAdd(&osup[vstart + qc[e]], 1u);
+                        else atomicAdd(&lsup[qc[e]], 1u);
+                    }
+                }
+            }
+            bits[gb[p] + kw] = mask;
+            found += (unsigned long long)__popc(mask);
+        }
+    }
+}
+
+// Counter slots rounded up to keep the int64 group arrays 16-byte aligned.
+__host__ __device__ __forceinline__ size_t counter_bytes(int d) {
+    return 4 * (((size_t)d + 3) & ~(size_t)3);
+}
+
+__host__ __device__ __forceinline__ size_t mid_wave_bytes(int dcap) {
+    return table_bytes(dcap) + counter_bytes(dcap) + GROUP_BYTES;
+}
+
+// One wavefront per item; pivots with |N_H(v)| <= dcap.
+__global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ orp,
+                                                   const int32_t *__restrict__ ocol,
+                                                   const int64_t *__restrict__ in_ptr,
+                                                   const uint64_t *__restrict__ in_pair,
+                                                   const int64_t *__restrict__ rowbase,
+                                                   uint32_t *__restrict__ bits,
+                                                   const int32_t *__restrict__ item_v,
+                                                   const uint32_t *__restrict__ item_first,
+                                                   int64_t nitems, int dcap,
+                                                   uint32_t *__restrict__ osup,
+                                                   unsigned long long *__restrict__ tri_total) {
+    extern __shared__ uint4 lds4[];
+    const int wpb = blockDim.x / TC_WAVE;
+    const int wv = threadIdx.x / TC_WAVE;
+    const int lane = __lane_id();
+    char *base = reinterpret_cast<char *>(lds4) + (size_t)wv * mid_wave_bytes(dcap);
+    const size_t tb = table_bytes(dcap);
+    const size_t nbmax = (size_t)1 << bucket_bits(dcap);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(base);
+    uint16_t *pos = reinterpret_cast<uint16_t *>(base + 16 * nbmax);
+    uint32_t *lsup = reinterpret_cast<uint32_t *>(base + tb);
+    char *grp = base + tb + counter_bytes(dcap);
+    int64_t *gx = reinterpret_cast<int64_t *>(grp);
+    int64_t *gs = gx + 64;
+    int64_t *gb = gs + 64;
+    int32_t *gt = reinterpret_cast<int32_t *>(gb + 64);
+    unsigned long long found = 0;
+    for (int64_t it = (int64_t)blockIdx.x * wpb + wv; it < nitems; it += (int64_t)gridDim.x * wpb) {
+        const int32_t v = item_v[it];
+        const int64_t first = item_first[it];
+        const int64_t pend = min(first + (int64_t)WAVE_ITEM_PAIRS, in_ptr[v + 1]);
+        const int64_t vstart = orp[v];
+        const int d = (int)(orp[v + 1] - vstart);
+        const RowTable t{keys, pos, bucket_bits(d)};
+        for (int j = lane; j < (4 << t.bb); j += TC_WAVE) keys[j] = EMPTY;
+        for (int j = lane; j < d; j += TC_WAVE) lsup[j] = 0;
+        for (int j = lane; j < d; j += TC_WAVE) table_insert(t, (uint32_t)ocol[vstart + j], j);
+        const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
+        for (int64_t g0 = first; g0 < pend; g0 += TC_WAVE)
+            mid_group<false>(orp, ocol, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t, hmax,
+                             lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
+        for (int j = lane; j < d; j += TC_WAVE) {
+            const uint32_t c = lsup[j];
+            if (c) atomicAdd(&osup[vstart + j], c);
+        }
+    }
+    found = tc_wave_sum(found);
+    if (lane == 0 && found) atomicAdd(tri_total, found);
+}
+
+static inline size_t mid_block_bytes(int dmax, int wpb, bool global_lookup) {
+    const size_t t = global_lookup ? 0 : table_bytes(dmax) + counter_bytes(dmax);
+    return t + (size_t)wpb * GROUP_BYTES;
+}
+
+// One workgroup per item; its wavefronts share the pivot's table and take
+// the item's 64-pair groups in turn.
+template <bool GLOBAL_LOOKUP>
+__global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ orp,
+                                                    const int32_t *__restrict__ ocol,
+                                                    const int64_t *__restrict__ in_ptr,
+                                                    const uint64_t *__restrict__ in_pair,
+                                                    const int64_t *__restrict__ rowbase,
+                                                    uint32_t *__restrict__ bits,
+                                                    const int32_t *__restrict__ item_v,
+                                                    const uint32_t *__restrict__ item_first,
+                                                    int64_t nitems, int dmax, int item_pairs,
+                                                    uint32_t *__restrict__ osup,
+                                                    unsigned long long *__restrict__ tri_total) {
+    extern __shared__ uint4 lds4[];
+    const int wpb = blockDim.x / TC_WAVE;
+    const int wv = threadIdx.x / TC_WAVE;
+    const int lane = __lane_id();
+    char *base = reinterpret_cast<char *>(lds4);
+    size_t tpart = 0;
+    uint32_t *keys = nullptr, *lsup = nullptr;
+    uint16_t *pos = nullptr;
+    if constexpr (!GLOBAL_LOOKUP) {
+        const size_t nbmax = (size_t)1 << bucket_bits(dmax);
+        keys = reinterpret_cast<uint32_t *>(base);
+        pos = reinterpret_cast<uint16_t *>(base + 16 * nbmax);
+        lsup = reinterpret_cast<uint32_t *>(base + table_bytes(dmax));
+        tpart = table_bytes(dmax) + counter_bytes(dmax);
+    }
+    char *grp = base + tpart + (size_t)wv * GROUP_BYTES;
+    int64_t *gx = reinterpret_cast<int64_t *>(grp);
+    int64_t *gs = gx + 64;
+    int64_t *gb = gs + 64;
+    int32_t *gt = reinterpret_cast<int32_t *>(gb + 64);
+    unsigned long long found = 0;
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int32_t v = item_v[it];
+        const int64_t first = item_first[it];
+        const int64_t pend = min(first + (int64_t)item_pairs, in_ptr[v + 1]);
+        const int64_t vstart = orp[v];
+        const int d = (int)(orp[v + 1] - vstart);
+        RowTable t{keys, pos, 0};
+        if constexpr (!GLOBAL_LOOKUP) {
+            t.bb = bucket_bits(d);
+            for (int j = threadIdx.x; j < (4 << t.bb); j += blockDim.x) keys[j] = EMPTY;
+            for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
+            __syncthreads();
+            for (int j = threadIdx.x; j < d; j += blockDim.x)
+                table_insert(t, (uint32_t)ocol[vstart + j], j);
+            __syncthreads();
+        }
+        const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
+        for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE)
+            mid_group<GLOBAL_LOOKUP>(orp, ocol, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t,
+                                     hmax, lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
+        if constexpr (!GLOBAL_LOOKUP) {
+            __syncthreads();
+            for (int j = threadIdx.x; j < d; j += blockDim.x) {
+                const uint32_t c = lsup[j];
+                if (c) atomicAdd(&osup[vstart + j], c);
+            }
+            __syncthreads();
+        }
+    }
+    found = tc_wave_sum(found);
+    if (lane == 0 && found) atomicAdd(tri_total, found);
+}
+
+// ---------------------------------------------------------------------------
+// Fold of the bit matrices: a group of GL lanes per row u (|N_H(u)| >= 2).
+//   row sums:    sup(u, N_H(u)[i]) += popcount(B_u row i)
+//   column sums: sup(u, N_H(u)[j]) += Σ_{i<j} B_u[i][j]
+// Column sums run over stripes of 32 columns; lane (stripe c, group g)
+// takes every row i ≡ g (mod G) that reaches the stripe, extracts that
+// row's 32 bits at the stripe's columns (row i's bit b is column i + 1 + b)
+// and adds them into 6 bit-sliced counter planes (a carry-save adder, up to
+// 63 rows), which are emptied into 32 integer counters every 63 rows.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void planes_flush(uint32_t (&pl)[6], uint32_t (&cnt)[32]) {
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v |= ((pl[k] >> b) & 1u) << k;
+        cnt[b] += v;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pl[k] = 0;
+}
+
+template <int GL>
+__global__ __launch_bounds__(256) void k_fold(const int32_t *__restrict__ rows, int64_t nrows,
+                                              const int64_t *__restrict__ orp,
+                                              const int64_t *__restrict__ rowbase,
+                                              const uint32_t *__restrict__ bits,
+                                              uint32_t *__restrict__ osup) {
+    const int sub = threadIdx.x % GL;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GL);
+    for (int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL; gi < nrows; gi += groups) {
+        const int32_t r = rows[gi];
+        const int64_t rs = orp[r];
+        const int64_t d = orp[r + 1] - rs;
+        const int64_t base = rowbase[r];
+        const int64_t sd = bit_words(d);
+        for (int64_t i = sub; i < d - 1; i += GL) {
+            const int64_t off = base + sd - bit_words(d - i);
+            const int64_t nw = (d - 1 - i + 31) >> 5;
+            uint32_t c = 0;
+            for (int64_t q = 0; q < nw; ++q) c += __popc(bits[off + q]);
+            if (c) atomicAdd(&osup[rs + i], c);
+        }
+        const int64_t nst = (d + 31) >> 5;
+        const int64_t G = nst >= GL ? 1 : GL / nst;
+        for (int64_t unit = sub; unit < nst * G; unit += GL) {
+            const int64_t c = unit % nst, g = unit / nst;
+            uint32_t cnt[32];
+#pragma unroll
+            for (int b = 0; b < 32; ++b) cnt[b] = 0;
+            uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
+            int fill = 0;
+            const int64_t imax = min(d - 2, 32 * c + 30);
+            for (int64_t i = g; i <= imax; i += G) {
+                const int64_t off = base + sd - bit_words(d - i);
+                const int64_t nw = (d - 1 - i + 31) >> 5;
+                const int64_t o = 32 * c - (i + 1);  // row-i bit of the stripe's first column
+                uint32_t w;
+                if (o >= 0) {
+                    const int64_t q = o >> 5;
+                    const int sh = (int)(o & 31);
+                    const uint32_t lo = q < nw ? bits[off + q] : 0u;
+                    const uint32_t hi = q + 1 < nw ? bits[off + q + 1] : 0u;
+                    w = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
+                } else {
+                    w = nw > 0 ? bits[off] << (int)(-o) : 0u;
+                }
+                uint32_t carry = w;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const uint32_t tk = pl[k] & carry;
+                    pl[k] ^= carry;
+                    carry = tk;
+                }
+                if (++fill == 63) {
+                    planes_flush(pl, cnt);
+                    fill = 0;
+                }
+            }
+            planes_flush(pl, cnt);
+#pragma unroll
+            for (int b = 0; b < 32; ++b) {
+                const int64_t j = 32 * c + b;
+                if (j < d && cnt[b]) atomicAdd(&osup[rs + j], cnt[b]);
+            }
+        }
+    }
+}
+
+__global__ void k_dplus_flags(int32_t n, const int64_t *__restrict__ orp, int lo, int hi,
+                              uint32_t *__restrict__ f) {
+    GRID_STRIDE(r, n) {
+        const int64_t d = orp[r + 1] - orp[r];
+        f[r] = (d >= lo && d <= hi) ? 1u : 0u;
+    }
+}
+
+__global__ void k_dplus_write(int32_t n, const int64_t *__restrict__ orp, int lo, int hi,
+                              const uint32_t *__restrict__ pos, int32_t *__restrict__ out) {
+    GRID_STRIDE(r, n) {
+        const int64_t d = orp[r + 1] - orp[r];
+        if (d >= lo && d <= hi) out[pos[r]] = (int32_t)r;
+    }
+}
+
+tc_status rows_by_dplus(const tc_graph *g, int lo, int hi, int32_t **out, int64_t *count,
+                        tc_scratch &keep, hipStream_t s) {
+    const int32_t n = g->n;
+    tc_scratch tmp(s);
+    uint32_t *pos = nullptr, *tot = nullptr;
+    TC_TRY(tmp.get(&pos, n));
+    TC_TRY(tmp.get(&tot, 1));
+    k_dplus_flags<<<grid_for(n), BK, 0, s>>>(n, g->orp, lo, hi, pos);
+    TC_LAUNCHED();
+    TC_TRY(tc_scan_u32(pos, pos, n, tot, s));
+    uint32_t h = 0;
+    TC_HIP(hipMemcpyAsync(&h, tot, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    *count = h;
+    TC_TRY(keep.get(out, h));
+    if (h > 0) {
+        k_dplus_write<<<grid_for(n), BK, 0, s>>>(n, g->orp, lo, hi, pos, *out);
+        TC_LAUNCHED();
+    }
+    return TC_OK;
+}
+
+__global__ void k_zero_words(uint32_t *__restrict__ p, int64_t words) {
+    GRID_STRIDE(i, words) p[i] = 0u;
+}
+
+__global__ void k_row_words(int32_t n, const int64_t *__restrict__ orp, int64_t *__restrict__ out) {
+    GRID_STRIDE(r, n) out[r] = bit_words(orp[r + 1] - orp[r]);
+}
+
+// Work per bin for the statistics: scan lengths of every pair, binned by
+// the pivot's |N_H|.
+__global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
+                            const int32_t *__restrict__ ocol, const uint64_t *__restrict__ in_pair,
+                            int light_max, int huge_min, unsigned long long *__restrict__ acc) {
+    GRID_STRIDE(i, m) {
+        const uint64_t pr = in_pair[i];
+        const uint32_t k = (uint32_t)pr;
+        const int32_t u = (int32_t)(pr >> 32);
+        const int32_t v = ocol[k];
+        const int64_t d = orp[v + 1] - orp[v];
+        const int64_t len = orp[u + 1] - (int64_t)k - 1;
+        if (d < 1) continue;
+        const int bin = d <= light_max ? 0 : (d < huge_min ? 1 : 2);
+        atomicAdd(&acc[3 + bin], (unsigned long long)len);
+        atomicAdd(&acc[8 + bin], 1ull);
+    }
+}
+
+__global__ void k_mid_pivots(int32_t n, const int64_t *__restrict__ orp,
+                             const int64_t *__restrict__ in_ptr, int light_max, int huge_min,
+                             unsigned long long *__restrict__ acc) {
+    GRID_STRIDE(v, n) {
+        const int64_t d = orp[v + 1] - orp[v];
+        if (d < 1 || in_ptr[v + 1] == in_ptr[v]) continue;
+        const int bin = d <= light_max ? 0 : (d < huge_min ? 1 : 2);
+        atomicAdd(&acc[bin], 1ull);
+    }
+}
+
+tc_status build_items(const tc_graph *g, int lo, int hi, int S, int32_t **item_v,
+                      uint32_t **item_first, int64_t *count, tc_scratch &keep, hipStream_t s) {
+    const int32_t n = g->n;
+    tc_scratch tmp(s);
+    uint32_t *cnt = nullptr, *off = nullptr, *tot = nullptr;
+    TC_TRY(tmp.get(&cnt, n));
+    TC_TRY(tmp.get(&off, n));
+    TC_TRY(tmp.get(&tot, 1));
+    k_item_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->in_ptr, lo, hi, S, cnt);
+    TC_LAUNCHED();
+    TC_TRY(tc_scan_u32(cnt, off, n, tot, s));
+    uint32_t h = 0;
+    TC_HIP(hipMemcpyAsync(&h, tot, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    *count = h;
+    TC_TRY(keep.get(item_v, h));
+    TC_TRY(keep.get(item_first, h));
+    if (h > 0) {
+        k_item_write<<<grid_for(n), BK, 0, s>>>(n, cnt, off, g->in_ptr, S, *item_v, *item_first);
+        TC_LAUNCHED();
+    }
+    return TC_OK;
+}
+
+}  // namespace
+
+// Builds in_ptr / in_pair (the transposed orientation) once per handle.
+tc_status tc_mid_prepare(tc_graph *g, hipStream_t s) {
+    if (g->in_pair) return TC_OK;
+    const int32_t n = g->n;
+    const int64_t m = g->m;
+    const int64_t nn = n > 0 ? n : 1;
+    TC_TRY(tc_graph_alloc(g, &g->in_ptr, nn + 1, s));
+    TC_TRY(tc_graph_alloc(g, &g->in_pair, m, s));
+    tc_scratch tmp(s);
+    uint32_t *key = nullptr, *key2 = nullptr, *st = nullptr, *en = nullptr;
+    uint64_t *val = nullptr, *val2 = nullptr;
+    int64_t *len = nullptr;
+    TC_TRY(tmp.get(&key, m));
+    TC_TRY(tmp.get(&key2, m));
+    TC_TRY(tmp.get(&val2, m));
+    TC_TRY(tmp.get(&st, nn));
+    TC_TRY(tmp.get(&en, nn));
+    TC_TRY(tmp.get(&len, nn));
+    val = g->in_pair;
+    k_slot_rows<<<grid_for(n), BK, 0, s>>>(n, g->orp, key, val, g->ocol);
+    TC_LAUNCHED();
+    uint64_t *vres = val, *vswap = val2;
+    TC_TRY(tc_sort_u32_u64(&key, &vres, &key2, &vswap, m, g->bits, s));
+    if (vres != g->in_pair)
+        TC_HIP(hipMemcpyAsync(g->in_pair, vres, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
+    TC_HIP(hipMemsetAsync(st, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemsetAsync(en, 0, sizeof(uint32_t) * nn, s));
+    k_in_runs<<<grid_for(m), BK, 0, s>>>(key, m, st, en);
+    TC_LAUNCHED();
+    k_in_len<<<grid_for(n), BK, 0, s>>>(n, st, en, len);
+    TC_LAUNCHED();
+    TC_TRY(tc_scan_i64(len, g->in_ptr, n, g->in_ptr + n, s));
+    // bit matrices: rowbase = exclusive scan of each row's word count
+    TC_TRY(tc_graph_alloc(g, &g->rowbase, nn + 1, s));
+    k_row_words<<<grid_for(n), BK, 0, s>>>(n, g->orp, len);
+    TC_LAUNCHED();
+    TC_TRY(tc_scan_i64(len, g->rowbase, n, g->rowbase + n, s));
+    int64_t words = 0;
+    TC_HIP(hipMemcpyAsync(&words, g->rowbase + n, 8, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    g->bit_words = words;
+    TC_TRY(tc_graph_alloc(g, &g->hitbits, words, s));
+    return TC_OK;
+}
+
+tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_entries,
+                       unsigned long long *found, hipStream_t s) {
+    TC_TRY(tc_mid_prepare(g, s));
+    const int light_max = t.light_max_dplus;
+    int huge_min = max_entries / 2 + 1;
+    if (huge_min <= light_max) huge_min = light_max + 1;
+    g->light_max = light_max;
+    g->huge_min = huge_min;
+
+    int wpb_block = t.heavy_block / TC_WAVE;
+    const int block_pairs = TC_WAVE * wpb_block * BLOCK_ITEM_GROUPS;
+    tc_scratch items(s);
+    int32_t *wv_v = nullptr, *bl_v = nullptr, *hu_v = nullptr;
+    uint32_t *wv_f = nullptr, *bl_f = nullptr, *hu_f = nullptr;
+    int64_t n_wave = 0, n_block = 0, n_huge = 0;
+    TC_TRY(build_items(g, 1, light_max, WAVE_ITEM_PAIRS, &wv_v, &wv_f, &n_wave, items, s));
+    TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, &bl_v, &bl_f, &n_block, items, s));
+    TC_TRY(build_items(g, huge_min, 0x7FFFFFFF, block_pairs, &hu_v, &hu_f, &n_huge, items, s));
+    g->n_light = n_wave;
+    g->n_heavy = n_block;
+    g->n_huge = n_huge;
+    // pairs whose pivot closes nothing are never scanned: their rows stay 0
+    if (g->bit_words > 0) {
+        int64_t zb = tc_div_up(g->bit_words, BK);
+        k_zero_words<<<(unsigned)(zb < 1048576 ? zb : 1048576), BK, 0, s>>>(g->hitbits, g->bit_words);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 5, s);
+
+    if (n_wave > 0) {
+        const size_t per_wave = mid_wave_bytes(light_max);
+        int wpb = t.light_block / TC_WAVE;
+        while (wpb > 1 && (size_t)wpb * per_wave > (size_t)lds_limit) --wpb;
+        int64_t blocks = tc_div_up(n_wave, wpb);
+        if (blocks > 262144) blocks = 262144;
+        k_mid_wave<<<(unsigned)blocks, wpb * TC_WAVE, (size_t)wpb * per_wave, s>>>(
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, wv_v, wv_f, n_wave,
+            light_max, g->osup, found);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 6, s);
+    if (n_block > 0) {
+        const int hmax = g->max_dplus < huge_min - 1 ? g->max_dplus : huge_min - 1;
+        const size_t lds = mid_block_bytes(hmax, wpb_block, false);
+        int64_t blocks = n_block < 1048576 ? n_block : 1048576;
+        k_mid_block<false><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bl_v, bl_f, n_block, hmax,
+            block_pairs, g->osup, found);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 7, s);
+    if (n_huge > 0) {
+        const size_t lds = mid_block_bytes(0, wpb_block, true);
+        int64_t blocks = n_huge < 1048576 ? n_huge : 1048576;
+        k_mid_block<true><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, hu_v, hu_f, n_huge, 0,
+            block_pairs, g->osup, found);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 8, s);
+    if (g->bit_words > 0) {
+        int32_t *small = nullptr, *big = nullptr;
+        int64_t ns = 0, nb = 0;
+        TC_TRY(rows_by_dplus(g, 2, 64, &small, &ns, items, s));
+        TC_TRY(rows_by_dplus(g, 65, 0x7FFFFFFF, &big, &nb, items, s));
+        if (ns > 0) {
+            int64_t fb = tc_div_up(ns, BK / 16);
+            k_fold<16><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK, 0, s>>>(
+                small, ns, g->orp, g->rowbase, g->hitbits, g->osup);
+            TC_LAUNCHED();
+        }
+        if (nb > 0) {
+            int64_t fb = tc_div_up(nb, BK / TC_WAVE);
+            k_fold<TC_WAVE><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK, 0, s>>>(
+                big, nb, g->orp, g->rowbase, g->hitbits, g->osup);
+            TC_LAUNCHED();
+        }
+    }
+    tc_prof_mark(g, 9, s);
+    return TC_OK;
+}
+
+tc_status tc_mid_stats(tc_graph *g, unsigned long long *acc, hipStream_t s) {
+    TC_TRY(tc_mid_prepare(g, s));
+    const int light_max = g->light_max > 0 ? g->light_max : 64;
+    const int huge_min = g->huge_min > 0 ? g->huge_min : 0x7FFFFFFF;
+    k_mid_stats<<<grid_for(g->m), BK, 0, s>>>(g->m, g->orp, g->ocol, g->in_pair, light_max,
+                                             huge_min, acc);
+    TC_LAUNCHED();
+    k_mid_pivots<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, g->in_ptr, light_max, huge_min, acc);
+    TC_LAUNCHED();
+    return TC_OK;
+}

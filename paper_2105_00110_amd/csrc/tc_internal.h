@@ -8,7 +8,7 @@
 #include "tc.h"
 
 #define TC_WAVE 64
-#define TC_PROF_MARKS 11
+#define TC_PROF_MARKS 12
 
 // ---------------------------------------------------------------------------
 // Error plumbing: internal functions return tc_status; HIP failures map to
@@ -31,7 +31,7 @@ tc_status tc_map_hip_error(hipError_t e);
 // Launch check: kernel launch errors surface through hipGetLastError().
 #define TC_LAUNCHED() TC_HIP(hipGetLastError())
 
-static inline int64_t tc_div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ static inline int64_t tc_div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 static inline int tc_bits_for(uint64_t max_value) {
     int b = 0;
@@ -91,6 +91,8 @@ tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s);
 tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s);
+tc_status tc_sort_u32_u64(uint32_t **keys, uint64_t **vals, uint32_t **tmp_keys,
+                          uint64_t **tmp_vals, int64_t n, int bits, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // The graph handle.
@@ -117,6 +119,14 @@ struct tc_graph {
     int64_t *orp = nullptr;                         // [n+1]
     int32_t *ocol = nullptr;                        // [m]
     uint32_t *o2e = nullptr;                        // [m] canonical edge of each oriented slot
+    // transposed orientation (middle-pivot counting): pairs grouped by the
+    // higher end v, entry = (u << 32) | slot of v in N_H(u)
+    int64_t *in_ptr = nullptr;                      // [n+1]
+    uint64_t *in_pair = nullptr;                    // [m]
+    // per-row triangular bit matrices of the middle-pivot scan
+    int64_t *rowbase = nullptr;                     // [n+1] first word of each row's matrix
+    uint32_t *hitbits = nullptr;                    // [bit_words]
+    int64_t bit_words = 0;
     // results
     uint32_t *osup = nullptr;                       // [m] support per oriented slot
     uint32_t *esup = nullptr;                       // [m] support per canonical edge
@@ -137,6 +147,7 @@ struct tc_graph {
 
     // bins of the last count: light 2..light_max, heavy ..huge_min-1, huge
     int32_t light_max = 0, huge_min = 0;
+    int32_t algo_used = 0;
 
     // profiling marks (see tc_prof_mark)
     bool prof = false;
@@ -146,7 +157,7 @@ struct tc_graph {
 
 // Profiling marks: 0 build start, 1 CSR built, 2 ranked, 3 oriented,
 // 4 compute start, 5 binned, 6 light counted, 7 heavy counted,
-// 8 huge counted, 9 tri/triG done, 10 aggregated.
+// 8 huge counted, 9 folded, 10 tri/triG done, 11 aggregated.
 bool tc_profiling_on();
 void tc_prof_mark(tc_graph *g, int idx, hipStream_t s);
 
@@ -158,6 +169,10 @@ tc_status tc_orient(tc_graph *g, hipStream_t s);
 tc_status tc_count(tc_graph *g, const tc_tuning *t, hipStream_t s);
 tc_status tc_aggregate(tc_graph *g, hipStream_t s);
 tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s);
+tc_status tc_mid_prepare(tc_graph *g, hipStream_t s);
+tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_entries,
+                       unsigned long long *found, hipStream_t s);
+tc_status tc_mid_stats(tc_graph *g, unsigned long long *acc, hipStream_t s);
 
 template <typename T>
 tc_status tc_graph_alloc(tc_graph *g, T **p, int64_t count, hipStream_t s) {

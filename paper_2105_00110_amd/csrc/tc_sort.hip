@@ -164,3 +164,8 @@ tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s) {
     return radix_sort<uint32_t, uint32_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s);
 }
+
+tc_status tc_sort_u32_u64(uint32_t **keys, uint64_t **vals, uint32_t **tmp_keys,
+                          uint64_t **tmp_vals, int64_t n, int bits, hipStream_t s) {
+    return radix_sort<uint32_t, uint64_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s);
+}

@@ -31,6 +31,10 @@ TC_ERR_UNSUPPORTED = -8
 TC_MEM_HOST = 0
 TC_MEM_DEVICE = 1
 
+TC_ALGO_AUTO = 0
+TC_ALGO_LOW_PIVOT = 1
+TC_ALGO_MID_PIVOT = 2
+
 _lib = None
 
 
@@ -43,7 +47,8 @@ class TCError(RuntimeError):
 
 class tc_tuning(ctypes.Structure):
     _fields_ = [("light_max_dplus", ctypes.c_int32), ("heavy_block", ctypes.c_int32),
-                ("light_block", ctypes.c_int32), ("lds_max_entries", ctypes.c_int32)]
+                ("light_block", ctypes.c_int32), ("lds_max_entries", ctypes.c_int32),
+                ("algorithm", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -79,10 +84,10 @@ _SIGS = {
 }
 
 STAGES = ["csr_build", "degree_rank", "orient", "bin", "count_light", "count_heavy",
-          "count_huge", "tri", "aggregate"]
+          "count_huge", "fold", "tri", "aggregate"]
 WORK_STATS = ["n", "m", "max_dplus", "rows_light", "rows_heavy", "rows_huge", "cand_light",
               "cand_heavy", "cand_huge", "merge_work", "wedges", "triangles", "edges_light",
-              "edges_heavy", "edges_huge"]
+              "edges_heavy", "edges_huge", "w_hash", "algorithm"]
 
 
 def load(path=None):

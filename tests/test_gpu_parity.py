@@ -104,12 +104,15 @@ def test_parity_random_tiny(tclib, seed):
     assert_parity(run_gpu(tclib, src, dst, n), ref)
 
 
-TUNINGS = [
-    None,
+_SCHEDULES = [
+    {},
     {"light_max_dplus": 2, "heavy_block": 64, "light_block": 64, "lds_max_entries": 16384},
     {"light_max_dplus": 1024, "heavy_block": 1024, "light_block": 1024, "lds_max_entries": 1024},
     {"light_max_dplus": 16, "heavy_block": 512, "light_block": 128, "lds_max_entries": 1024},
+    {"light_max_dplus": 37, "heavy_block": 192, "light_block": 320, "lds_max_entries": 2048},
 ]
+# every schedule under both pivot choices (low = 1, middle = 2)
+TUNINGS = [None] + [dict(sc, algorithm=a) for a in (1, 2) for sc in _SCHEDULES]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNINGS)))
