@@ -107,6 +107,9 @@ const char *tc_status_string(int32_t status);
  *                    streamed work is the number of oriented wedges.
  *                    In the middle-pivot form "rows" are the pivots v and
  *                    the bins above are taken on |N_H(v)| of the pivot.
+ *   item_pairs       middle pivot only: lower neighbours of one pivot per
+ *                    work item of a wavefront (a workgroup item takes this
+ *                    many per wavefront); 64..65536, a multiple of 64.
  * ---------------------------------------------------------------------- */
 #define TC_ALGO_AUTO 0
 #define TC_ALGO_LOW_PIVOT 1
@@ -118,6 +121,7 @@ typedef struct tc_tuning {
     int32_t light_block;
     int32_t lds_max_entries;
     int32_t algorithm;
+    int32_t item_pairs;
 } tc_tuning;
 
 /* Writes the built-in defaults to *t. */

@@ -257,11 +257,12 @@ tc_status select_rows(const tc_graph *g, int lo, int hi, int32_t *out, int64_t *
 
 tc_status tc_tuning_default(tc_tuning *t) {
     if (!t) return TC_ERR_INVALID_ARG;
-    t->light_max_dplus = 64;
+    t->light_max_dplus = 512;
     t->heavy_block = 256;
     t->light_block = 256;
     t->lds_max_entries = 4096;
     t->algorithm = TC_ALGO_AUTO;
+    t->item_pairs = 512;
     return TC_OK;
 }
 
@@ -271,7 +272,8 @@ static bool tuning_valid(const tc_tuning *t) {
            t->heavy_block <= 1024 && t->heavy_block % 64 == 0 && t->light_block >= 64 &&
            t->light_block <= 1024 && t->light_block % 64 == 0 && pow2(t->lds_max_entries) &&
            t->lds_max_entries >= 1024 && t->lds_max_entries <= 16384 && t->algorithm >= 0 &&
-           t->algorithm <= 2;
+           t->algorithm <= 2 && t->item_pairs >= 64 && t->item_pairs <= 65536 &&
+           t->item_pairs % 64 == 0;
 }
 
 tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {

@@ -43,8 +43,6 @@ namespace {
 using namespace tc_tab;
 
 constexpr int BK = 256;
-constexpr int WAVE_ITEM_PAIRS = 256;  // pairs per wavefront item
-constexpr int BLOCK_ITEM_GROUPS = 4;  // 64-pair groups per wavefront in a workgroup item
 constexpr size_t GROUP_BYTES = 64 * 8 * 3 + 64 * 4;  // gx, gs, gb (int64), gt (int32)
 
 // Words of the bit rows of a row with d entries: Σ_{t=1}^{d-1} ceil(t/32).
@@ -215,7 +213,7 @@ __global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ o
                                                    uint32_t *__restrict__ bits,
                                                    const int32_t *__restrict__ item_v,
                                                    const uint32_t *__restrict__ item_first,
-                                                   int64_t nitems, int dcap,
+                                                   int64_t nitems, int dcap, int item_pairs,
                                                    uint32_t *__restrict__ osup,
                                                    unsigned long long *__restrict__ tri_total) {
     extern __shared__ uint4 lds4[];
@@ -237,7 +235,7 @@ __global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ o
     for (int64_t it = (int64_t)blockIdx.x * wpb + wv; it < nitems; it += (int64_t)gridDim.x * wpb) {
         const int32_t v = item_v[it];
         const int64_t first = item_first[it];
-        const int64_t pend = min(first + (int64_t)WAVE_ITEM_PAIRS, in_ptr[v + 1]);
+        const int64_t pend = min(first + (int64_t)item_pairs, in_ptr[v + 1]);
         const int64_t vstart = orp[v];
         const int d = (int)(orp[v + 1] - vstart);
         const RowTable t{keys, pos, bucket_bits(d)};
@@ -419,6 +417,117 @@ __global__ __launch_bounds__(256) void k_fold(const int32_t *__restrict__ rows, 
     }
 }
 
+// The 32 bits of row i of B_u at the columns of stripe c (row i's bit b
+// is column i + 1 + b; bits outside the row read as 0).  lo/hi are the two
+// row words the stripe can touch, already loaded.
+__device__ __forceinline__ uint32_t stripe_bits(int64_t o, uint32_t lo, uint32_t hi) {
+    if (o < 0) return lo << (int)(-o);
+    const int sh = (int)(o & 31);
+    return sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
+}
+
+// Big rows (|N_H(u)| > 64): one wavefront per row, column sums split into
+// units of (stripe c, 63 consecutive rows) dealt round-robin to the lanes,
+// each unit's 32 counts added into the wavefront's LDS column counters
+// (or, for rows longer than the LDS counters, straight to device memory).
+constexpr int FOLD_RC = 63;  // rows per unit: 6 counter planes hold up to 63
+
+__global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ rows, int64_t nrows,
+                                                  const int64_t *__restrict__ orp,
+                                                  const int64_t *__restrict__ rowbase,
+                                                  const uint32_t *__restrict__ bits,
+                                                  uint32_t *__restrict__ osup, int dcap) {
+    extern __shared__ uint32_t colc_all[];
+    const int lane = __lane_id();
+    const int wv = threadIdx.x / TC_WAVE;
+    uint32_t *colc = colc_all + (size_t)wv * dcap;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / TC_WAVE);
+    for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x / TC_WAVE) + wv; gi < nrows; gi += waves) {
+        const int32_t r = rows[gi];
+        const int64_t rs = orp[r];
+        const int64_t d = orp[r + 1] - rs;
+        const int64_t base = rowbase[r];
+        const int64_t sd = bit_words(d);
+        const bool in_lds = d <= dcap;
+        if (in_lds)
+            for (int64_t j = lane; j < d; j += TC_WAVE) colc[j] = 0;
+        for (int64_t i = lane; i < d - 1; i += TC_WAVE) {
+            const int64_t off = base + sd - bit_words(d - i);
+            const int64_t nw = (d - 1 - i + 31) >> 5;
+            uint32_t c = 0;
+            for (int64_t q0 = 0; q0 < nw; q0 += 8) {
+                uint32_t x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = q0 + e < nw ? bits[off + q0 + e] : 0u;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) c += __popc(x[e]);
+            }
+            if (c) atomicAdd(&osup[rs + i], c);
+        }
+        // unit u = (stripe u / nch, chunk u % nch); all lanes take units in
+        // lockstep rounds (chunks past a stripe's last row are empty)
+        const int64_t nst = (d + 31) >> 5;
+        const int64_t nch = (d - 1 + FOLD_RC - 1) / FOLD_RC;
+        for (int64_t u0 = 0; u0 < nst * nch; u0 += TC_WAVE) {
+            const int64_t unit = u0 + lane;
+            if (unit >= nst * nch) continue;
+            const int64_t c = unit / nch, ch = unit % nch;
+            const int64_t nrow = min(d - 1, 32 * c + 31);  // rows reaching stripe c
+            const int64_t i0 = ch * FOLD_RC;
+            const int64_t i1 = min(nrow, i0 + FOLD_RC);
+            if (i0 >= i1) continue;
+            uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
+            // 8 rows at a time: all 16 word loads are issued before use
+            for (int64_t ib = i0; ib < i1; ib += 8) {
+                uint32_t lo[8], hi[8];
+                int64_t oo[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int64_t i = ib + e;
+                    lo[e] = 0u;
+                    hi[e] = 0u;
+                    oo[e] = 0;
+                    if (i < i1) {
+                        const int64_t off = base + sd - bit_words(d - i);
+                        const int64_t nw = (d - 1 - i + 31) >> 5;
+                        const int64_t o = 32 * c - (i + 1);
+                        const int64_t q = o < 0 ? 0 : (o >> 5);
+                        oo[e] = o;
+                        if (q < nw) lo[e] = bits[off + q];
+                        if (o >= 0 && q + 1 < nw) hi[e] = bits[off + q + 1];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    uint32_t carry = stripe_bits(oo[e], lo[e], hi[e]);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const uint32_t tk = pl[k] & carry;
+                        pl[k] ^= carry;
+                        carry = tk;
+                    }
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 32; ++b) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) v |= ((pl[k] >> b) & 1u) << k;
+                const int64_t j = 32 * c + b;
+                if (v && j < d) {
+                    if (in_lds) atomicAdd(&colc[j], v);
+                    else atomicAdd(&osup[rs + j], v);
+                }
+            }
+        }
+        if (in_lds)
+            for (int64_t j = lane; j < d; j += TC_WAVE) {
+                const uint32_t v = colc[j];
+                if (v) atomicAdd(&osup[rs + j], v);
+            }
+    }
+}
+
 __global__ void k_dplus_flags(int32_t n, const int64_t *__restrict__ orp, int lo, int hi,
                               uint32_t *__restrict__ f) {
     GRID_STRIDE(r, n) {
@@ -470,6 +579,7 @@ __global__ void k_row_words(int32_t n, const int64_t *__restrict__ orp, int64_t 
 __global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
                             const int32_t *__restrict__ ocol, const uint64_t *__restrict__ in_pair,
                             int light_max, int huge_min, unsigned long long *__restrict__ acc) {
+    unsigned long long sums[6] = {0, 0, 0, 0, 0, 0};  // cand per bin, pairs per bin
     GRID_STRIDE(i, m) {
         const uint64_t pr = in_pair[i];
         const uint32_t k = (uint32_t)pr;
@@ -479,8 +589,13 @@ __global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
         const int64_t len = orp[u + 1] - (int64_t)k - 1;
         if (d < 1) continue;
         const int bin = d <= light_max ? 0 : (d < huge_min ? 1 : 2);
-        atomicAdd(&acc[3 + bin], (unsigned long long)len);
-        atomicAdd(&acc[8 + bin], 1ull);
+        sums[bin] += (unsigned long long)len;
+        sums[3 + bin] += 1ull;
+    }
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        const unsigned long long v = tc_wave_sum(sums[b]);
+        if (__lane_id() == 0 && v) atomicAdd(&acc[b < 3 ? 3 + b : 5 + b], v);
     }
 }
 
@@ -576,12 +691,13 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     g->huge_min = huge_min;
 
     int wpb_block = t.heavy_block / TC_WAVE;
-    const int block_pairs = TC_WAVE * wpb_block * BLOCK_ITEM_GROUPS;
+    const int wave_pairs = t.item_pairs;
+    const int block_pairs = t.item_pairs * wpb_block;
     tc_scratch items(s);
     int32_t *wv_v = nullptr, *bl_v = nullptr, *hu_v = nullptr;
     uint32_t *wv_f = nullptr, *bl_f = nullptr, *hu_f = nullptr;
     int64_t n_wave = 0, n_block = 0, n_huge = 0;
-    TC_TRY(build_items(g, 1, light_max, WAVE_ITEM_PAIRS, &wv_v, &wv_f, &n_wave, items, s));
+    TC_TRY(build_items(g, 1, light_max, wave_pairs, &wv_v, &wv_f, &n_wave, items, s));
     TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, &bl_v, &bl_f, &n_block, items, s));
     TC_TRY(build_items(g, huge_min, 0x7FFFFFFF, block_pairs, &hu_v, &hu_f, &n_huge, items, s));
     g->n_light = n_wave;
@@ -603,7 +719,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         if (blocks > 262144) blocks = 262144;
         k_mid_wave<<<(unsigned)blocks, wpb * TC_WAVE, (size_t)wpb * per_wave, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, wv_v, wv_f, n_wave,
-            light_max, g->osup, found);
+            light_max, wave_pairs, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 6, s);
@@ -639,8 +755,11 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         }
         if (nb > 0) {
             int64_t fb = tc_div_up(nb, BK / TC_WAVE);
-            k_fold<TC_WAVE><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK, 0, s>>>(
-                big, nb, g->orp, g->rowbase, g->hitbits, g->osup);
+            int dcap = g->max_dplus < 8192 ? g->max_dplus : 8192;
+            dcap = (dcap + 3) & ~3;
+            k_fold_big<<<(unsigned)(fb < 1048576 ? fb : 1048576), BK,
+                         (size_t)(BK / TC_WAVE) * dcap * sizeof(uint32_t), s>>>(
+                big, nb, g->orp, g->rowbase, g->hitbits, g->osup, dcap);
             TC_LAUNCHED();
         }
     }
