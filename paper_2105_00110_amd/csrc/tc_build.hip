@@ -317,7 +317,9 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     tc_scratch tmp(s);
     int64_t nn = n > 0 ? n : 1;
     TC_TRY(tc_graph_alloc(g, &g->orp, nn + 1, s));
-    TC_TRY(tc_graph_alloc(g, &g->ocol, m, s));
+    // TC_OCOL_PAD trailing entries let the counting kernels load whole
+    // 32-entry runs without bounds tests (entries past a run are masked)
+    TC_TRY(tc_graph_alloc(g, &g->ocol, m + TC_OCOL_PAD, s));
     TC_TRY(tc_graph_alloc(g, &g->o2e, m, s));
     g->max_dplus = 0;
     if (m == 0) {

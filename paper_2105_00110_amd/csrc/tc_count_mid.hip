@@ -161,9 +161,14 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
             const int64_t kw = x - gx[p];
             const int64_t c0 = gs[p] + 32 * kw;
             const int cnt = min(32, gt[p] - 32 * (int)kw);
+            // whole 32-entry run (the array is padded past its end);
+            // entries past the tail are masked to EMPTY
             uint32_t ww[32];
 #pragma unroll
-            for (int b = 0; b < 32; ++b) ww[b] = b < cnt ? (uint32_t)ocol[c0 + b] : EMPTY;
+            for (int b = 0; b < 32; ++b) {
+                const uint32_t v = (uint32_t)ocol[c0 + b];
+                ww[b] = b < cnt ? v : EMPTY;
+            }
             // probe in batches of 8 (EMPTY, past the tail, is above every
             // rank and is never looked up); apply each batch's hits at once
             uint32_t mask = 0;
@@ -182,10 +187,13 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                 }
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    if (qc[e] >= 0) {
-                        mask |= 1u << (c + e);
-                        if constexpr (GLOBAL_LOOKUP) atomicAdd(&osup[vstart + qc[e]], 1u);
-                        else atomicAdd(&lsup[qc[e]], 1u);
+                    const bool hit = qc[e] >= 0;
+                    mask |= (hit ? 1u : 0u) << (c + e);
+                    if constexpr (GLOBAL_LOOKUP) {
+                        if (hit) atomicAdd(&osup[vstart + qc[e]], 1u);
+                    } else {
+                        // a miss adds 0 to this lane's spare counter: no branch
+                        atomicAdd(&lsup[hit ? qc[e] : dv + lane], hit ? 1u : 0u);
                     }
                 }
             }
@@ -196,8 +204,9 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
 }
 
 // Counter slots rounded up to keep the int64 group arrays 16-byte aligned.
+// (plus one spare slot per lane that branch-free misses add 0 to)
 __host__ __device__ __forceinline__ size_t counter_bytes(int d) {
-    return 4 * (((size_t)d + 3) & ~(size_t)3);
+    return 4 * ((((size_t)d + 3) & ~(size_t)3) + TC_WAVE);
 }
 
 __host__ __device__ __forceinline__ size_t mid_wave_bytes(int dcap) {

@@ -9,6 +9,7 @@
 
 #define TC_WAVE 64
 #define TC_PROF_MARKS 12
+#define TC_OCOL_PAD 64
 
 // ---------------------------------------------------------------------------
 // Error plumbing: internal functions return tc_status; HIP failures map to

@@ -26,8 +26,11 @@ struct RowTable {
     int bb;
 };
 
+// Bucket of a key: a multiplicative hash with the full-rate 24-bit
+// multiplier (the key's bits above 20 are folded in first).
 __device__ __forceinline__ uint32_t bucket_of(uint32_t key, int bb) {
-    return bb == 0 ? 0u : (key * 0x9E3779B1u) >> (32 - bb);
+    const uint32_t h = __umul24(key ^ (key >> 20), 0x9E3779u);
+    return bb == 0 ? 0u : h >> (32 - bb);
 }
 
 __device__ __forceinline__ void table_insert(const RowTable &t, uint32_t key, uint32_t p) {
@@ -72,7 +75,9 @@ __device__ __forceinline__ int table_find(const RowTable &t, uint32_t key) {
 
 // Probes N keys at once: the N first-bucket reads are all issued before
 // any result is used, so their LDS latencies overlap.  Keys above limit
-// (EMPTY included) are not looked up and give -1.
+// (EMPTY included) are not members and give -1.  Everything on the common
+// path is branch-free; a full bucket without the key (rare at load factor
+// <= 1/2) is followed up behind one wave-uniform test per batch.
 template <int N>
 __device__ __forceinline__ void table_find_n(const RowTable &t, const uint32_t (&key)[N],
                                              uint32_t limit, int (&q)[N]) {
@@ -85,21 +90,35 @@ __device__ __forceinline__ void table_find_n(const RowTable &t, const uint32_t (
         b[e] = bucket_of(key[e], t.bb);
         k[e] = kb[b[e]];
     }
+    int s[N];
+    uint32_t more = 0;
 #pragma unroll
     for (int e = 0; e < N; ++e) {
-        const bool valid = key[e] <= limit;
-        int s = valid ? slot_in(k[e], key[e]) : -1;
-        if (valid && s < 0 && k[e].w != EMPTY) {  // full bucket: keep looking (rare)
-            uint32_t bb = b[e];
-            uint4 kk = k[e];
-            while (s < 0 && kk.w != EMPTY) {
-                bb = (bb + 1) & mask;
-                kk = kb[bb];
-                s = slot_in(kk, key[e]);
+        s[e] = slot_in(k[e], key[e]);
+        const bool m = (key[e] <= limit) & (s[e] < 0) & (k[e].w != EMPTY);
+        more |= (uint32_t)m << e;
+    }
+    if (__builtin_expect(__ballot(more != 0) != 0ull, 0)) {
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            if ((more >> e) & 1u) {
+                uint32_t bb = b[e];
+                uint4 kk = k[e];
+                int ss = -1;
+                while (ss < 0 && kk.w != EMPTY) {
+                    bb = (bb + 1) & mask;
+                    kk = kb[bb];
+                    ss = slot_in(kk, key[e]);
+                }
+                b[e] = bb;
+                s[e] = ss;
             }
-            b[e] = bb;
         }
-        q[e] = s < 0 ? -1 : (int)t.pos[4 * b[e] + s];
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const int p = (int)t.pos[4 * b[e] + (s[e] < 0 ? 0 : s[e])];
+        q[e] = (key[e] <= limit && s[e] >= 0) ? p : -1;
     }
 }
 
