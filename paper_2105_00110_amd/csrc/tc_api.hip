@@ -150,7 +150,7 @@ void free_graph_arrays(tc_graph *g, hipStream_t s) {
     void *arrs[] = {g->eu,   g->ev,   g->row_ptr, g->col,  g->sym2e, g->rank, g->perm,
                     g->orp,  g->ocol, g->o2e,     g->osup, g->esup,  g->flag, g->tri,
                     g->num,  g->tcv,  g->triG,    g->vtx_off, g->err, g->bin_rows,
-                    g->in_ptr, g->in_pair, g->rowbase, g->hitbits};
+                    g->in_ptr, g->in_pair, g->rowbase, g->hitbits, g->orow};
     for (void *p : arrs) tc_dev_free(p, s);
 }
 

@@ -16,6 +16,8 @@
 //     higher-ordered neighbours N_H of the rank-r vertex, ascending.  This
 //     is the paper's split of N(v) into N_L(v) | N_H(v) (Lemma 1's proof),
 //     stored as its own compact array for the counting kernels.
+#include <stdlib.h>
+
 #include "tc_internal.h"
 
 namespace {
@@ -176,21 +178,316 @@ __global__ void k_orient_keys(int64_t m, const int32_t *__restrict__ eu, const i
 }
 
 __global__ void k_orient_split(int64_t m, const uint64_t *__restrict__ okey, int bits,
-                               int32_t *__restrict__ ocol) {
+                               int32_t *__restrict__ ocol, int32_t *__restrict__ orow) {
     const uint64_t mask = (1ull << bits) - 1;
-    GRID_STRIDE(k, m) ocol[k] = (int32_t)(okey[k] & mask);
+    GRID_STRIDE(k, m) {
+        ocol[k] = (int32_t)(okey[k] & mask);
+        orow[k] = (int32_t)(okey[k] >> bits);
+    }
 }
 
 __global__ void k_run_len64(int32_t n, const uint32_t *__restrict__ s, const uint32_t *__restrict__ e,
                             int64_t *__restrict__ len, uint32_t *__restrict__ maxlen) {
+    // one atomic per wavefront: a single word hit by every thread serialises
+    uint32_t mx = 0;
     GRID_STRIDE(x, n) {
         uint32_t d = e[x] - s[x];
         len[x] = d;
-        if (d > 0) atomicMax(maxlen, d);
+        mx = d > mx ? d : mx;
+    }
+    mx = tc_wave_max(mx);
+    if (__lane_id() == 0 && mx) atomicMax(maxlen, mx);
+}
+
+// ---------------------------------------------------------------------------
+// Orientation without a global sort (every row at most SEG_MAX entries):
+//   pass 1  d+ of every rank row, counted over the symmetric rows;
+//   pass 2  each row's higher-ordered neighbours are gathered into LDS,
+//           placed by rank (position = number of smaller keys: the keys of
+//           a row are distinct) and written to ocol/o2e, with the row of
+//           every slot in orow.
+// ---------------------------------------------------------------------------
+constexpr int SEG_MAX = 4096;
+constexpr int SEG_WAVE = 64;        // rows up to this many entries: one wavefront
+constexpr int64_t SCAN_BIG = 4096;  // symmetric rows longer than this: a workgroup
+
+// d+ of every rank row: each canonical edge adds one to the row of its
+// lower-ordered endpoint.  A row receives at most d+ additions, so the
+// contention per word is bounded by the largest out-degree.
+__global__ void k_count_higher(int64_t m, const int32_t *__restrict__ eu,
+                               const int32_t *__restrict__ ev, const int32_t *__restrict__ rank,
+                               unsigned long long *__restrict__ dplus) {
+    // Canonical edges come sorted by their smaller id, so neighbouring lanes
+    // often add to the same row: each run of equal rows in the wavefront
+    // is added once, by its first lane.
+    const int lane = __lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; e0 < m; e0 += stride) {
+        const int64_t e = e0 + lane;
+        const bool valid = e < m;
+        int32_t t = -1;
+        if (valid) {
+            const int32_t a = rank[eu[e]], b = rank[ev[e]];
+            t = a < b ? a : b;
+        }
+        const int32_t prev = __shfl_up(t, 1, TC_WAVE);
+        const bool head = valid && (lane == 0 || prev != t);
+        const uint64_t heads = __ballot(head);
+        const uint64_t valids = __ballot(valid);
+        if (head) {
+            const uint64_t later = heads & ~((2ull << lane) - 1);  // heads above this lane
+            const int end = later ? __ffsll((long long)later) - 1 : 64 - __clzll((long long)valids);
+            atomicAdd(&dplus[t], (unsigned long long)(end - lane));
+        }
     }
 }
 
+__global__ void k_max_i64(int32_t n, const int64_t *__restrict__ v, uint32_t *__restrict__ dmax) {
+    uint32_t mx = 0;
+    GRID_STRIDE(x, n) {
+        const uint32_t d = (uint32_t)v[x];
+        mx = d > mx ? d : mx;
+    }
+    mx = tc_wave_max(mx);
+    if (__lane_id() == 0 && mx) atomicMax(dmax, mx);
+}
+
+// Gathers the higher-ordered neighbours of vertex x into LDS (keys = ranks,
+// values = canonical edge ids), places them by rank and writes row rank(x).
+// GL lanes (a wavefront or a workgroup) handle the row; buf holds up to cap
+// entries.
+template <int GL>
+__device__ __forceinline__ void orient_row(int32_t x, const int64_t *__restrict__ row_ptr,
+                                           const int32_t *__restrict__ col,
+                                           const uint32_t *__restrict__ sym2e,
+                                           const int32_t *__restrict__ rank,
+                                           const int64_t *__restrict__ orp,
+                                           int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
+                                           int32_t *__restrict__ orow, uint32_t *bkey,
+                                           uint32_t *bval, uint32_t *fill, int tid) {
+    const int32_t rx = rank[x];
+    const int64_t ob = orp[rx];
+    const int d = (int)(orp[rx + 1] - ob);
+    if (d == 0) return;
+    const int64_t b = row_ptr[x], e = row_ptr[x + 1];
+    for (int64_t p0 = b; p0 < e; p0 += GL) {
+        const int64_t p = p0 + tid;
+        uint32_t ry = 0, ed = 0;
+        bool keep = false;
+        if (p < e) {
+            ry = (uint32_t)rank[col[p]];
+            keep = ry > (uint32_t)rx;
+            ed = sym2e[p];
+        }
+        const uint64_t bal = __ballot(keep);
+        const uint32_t before = (uint32_t)__popcll(bal & tc_lanemask_lt());
+        uint32_t base = 0;
+        if (__lane_id() == 0 && bal) base = atomicAdd(fill, (uint32_t)__popcll(bal));
+        base = __shfl(base, 0, TC_WAVE);
+        if (keep) {
+            bkey[base + before] = ry;
+            bval[base + before] = ed;
+        }
+    }
+    if (GL > TC_WAVE) __syncthreads();
+    for (int i = tid; i < d; i += GL) {
+        const uint32_t key = bkey[i];
+        int pos = 0;
+        for (int j = 0; j < d; ++j) pos += bkey[j] < key ? 1 : 0;
+        const int64_t k = ob + pos;
+        ocol[k] = (int32_t)key;
+        o2e[k] = bval[i];
+        orow[k] = rx;
+    }
+}
+
+// One wavefront per vertex whose row is short and has at most SEG_WAVE
+// higher-ordered neighbours.
+__global__ __launch_bounds__(256) void k_orient_wave(
+    int32_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const uint32_t *__restrict__ sym2e, const int32_t *__restrict__ rank,
+    const int64_t *__restrict__ orp, int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
+    int32_t *__restrict__ orow) {
+    __shared__ uint32_t sk[4][SEG_WAVE], sv[4][SEG_WAVE], sf[4];
+    const int wv = threadIdx.x / TC_WAVE;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t x = (int64_t)blockIdx.x * 4 + wv; x < n; x += waves) {
+        const int32_t rx = rank[x];
+        const int64_t d = orp[rx + 1] - orp[rx];
+        if (d == 0 || d > SEG_WAVE || row_ptr[x + 1] - row_ptr[x] > SCAN_BIG) continue;
+        if (__lane_id() == 0) sf[wv] = 0;
+        orient_row<TC_WAVE>((int32_t)x, row_ptr, col, sym2e, rank, orp, ocol, o2e, orow, sk[wv],
+                            sv[wv], &sf[wv], __lane_id());
+    }
+}
+
+// One workgroup per listed vertex (many higher neighbours or a long row).
+// The row is gathered as packed (rank << 32 | edge) words, padded with
+// all-ones words to a power of two and put in order by a bitonic sort in
+// LDS: log2(P)(log2(P)+1)/2 compare-exchange rounds instead of the
+// quadratic placement, which costs d^2 / 256 reads per thread on long rows.
+__global__ __launch_bounds__(256) void k_orient_block(
+    const int32_t *__restrict__ list, int64_t nlist, const int64_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col, const uint32_t *__restrict__ sym2e,
+    const int32_t *__restrict__ rank, const int64_t *__restrict__ orp, int32_t *__restrict__ ocol,
+    uint32_t *__restrict__ o2e, int32_t *__restrict__ orow) {
+    __shared__ uint64_t sk[SEG_MAX];
+    __shared__ uint32_t sf;
+    const int tid = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < nlist; i += gridDim.x) {
+        const int32_t x = list[i];
+        const int32_t rx = rank[x];
+        const int64_t ob = orp[rx];
+        const int d = (int)(orp[rx + 1] - ob);
+        if (tid == 0) sf = 0;
+        __syncthreads();
+        const int64_t b = row_ptr[x], e = row_ptr[x + 1];
+        for (int64_t p0 = b; p0 < e; p0 += 256) {
+            const int64_t p = p0 + tid;
+            uint64_t w = 0;
+            bool keep = false;
+            if (p < e) {
+                const uint32_t ry = (uint32_t)rank[col[p]];
+                keep = ry > (uint32_t)rx;
+                w = ((uint64_t)ry << 32) | sym2e[p];
+            }
+            const uint64_t bal = __ballot(keep);
+            const uint32_t before = (uint32_t)__popcll(bal & tc_lanemask_lt());
+            uint32_t base = 0;
+            if (__lane_id() == 0 && bal) base = atomicAdd(&sf, (uint32_t)__popcll(bal));
+            base = __shfl(base, 0, TC_WAVE);
+            if (keep) sk[base + before] = w;
+        }
+        int P = 1;
+        while (P < d) P <<= 1;
+        for (int j = d + tid; j < P; j += 256) sk[j] = ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = tid; t < (P >> 1); t += 256) {
+                    // t-th pair of this round: lower index a, partner a + j
+                    const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                    const uint64_t va = sk[a], vb = sk[a + j];
+                    const bool up = (a & k) == 0;
+                    if ((va > vb) == up) {
+                        sk[a] = vb;
+                        sk[a + j] = va;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int t = tid; t < d; t += 256) {
+            const uint64_t w = sk[t];
+            ocol[ob + t] = (int32_t)(w >> 32);
+            o2e[ob + t] = (uint32_t)w;
+            orow[ob + t] = rx;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_block_rows_flags(int32_t n, const int64_t *__restrict__ row_ptr,
+                                   const int32_t *__restrict__ rank,
+                                   const int64_t *__restrict__ orp, uint32_t *__restrict__ f) {
+    GRID_STRIDE(x, n) {
+        const int32_t rx = rank[x];
+        const int64_t d = orp[rx + 1] - orp[rx];
+        f[x] = (d > 0 && (d > SEG_WAVE || row_ptr[x + 1] - row_ptr[x] > SCAN_BIG)) ? 1u : 0u;
+    }
+}
+
+__global__ void k_compact_flags(int32_t n, const uint32_t *__restrict__ f,
+                                const uint32_t *__restrict__ pos, int32_t *__restrict__ out) {
+    GRID_STRIDE(x, n) if (f[x]) out[pos[x]] = (int32_t)x;
+}
+
 }  // namespace
+
+static tc_status orient_sorted(tc_graph *g, hipStream_t s);
+
+// Lists the vertices whose flag is set (flags in f, n entries).
+static tc_status compact_vertices(int32_t n, uint32_t *f, int32_t *out, int64_t *count,
+                                  hipStream_t s) {
+    tc_scratch tmp(s);
+    uint32_t *pos = nullptr, *tot = nullptr;
+    TC_TRY(tmp.get(&pos, n));
+    TC_TRY(tmp.get(&tot, 1));
+    TC_TRY(tc_scan_u32(f, pos, n, tot, s));
+    k_compact_flags<<<grid_for(n), BK, 0, s>>>(n, f, pos, out);
+    TC_LAUNCHED();
+    uint32_t h = 0;
+    TC_HIP(hipMemcpyAsync(&h, tot, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    *count = h;
+    return TC_OK;
+}
+
+tc_status tc_orient(tc_graph *g, hipStream_t s) {
+    const int32_t n = g->n;
+    const int64_t m = g->m;
+    int64_t nn = n > 0 ? n : 1;
+    TC_TRY(tc_graph_alloc(g, &g->orp, nn + 1, s));
+    // TC_OCOL_PAD trailing entries let the counting kernels load whole
+    // 32-entry runs without bounds tests (entries past a run are masked)
+    TC_TRY(tc_graph_alloc(g, &g->ocol, m + TC_OCOL_PAD, s));
+    TC_TRY(tc_graph_alloc(g, &g->o2e, m, s));
+    TC_TRY(tc_graph_alloc(g, &g->orow, m, s));
+    g->max_dplus = 0;
+    if (m == 0) {
+        TC_HIP(hipMemsetAsync(g->orp, 0, sizeof(int64_t) * (nn + 1), s));
+        tc_prof_mark(g, 3, s);
+        return TC_OK;
+    }
+    tc_scratch tmp(s);
+    int64_t *dplus = nullptr;
+    uint32_t *d_max = nullptr, *flags = nullptr;
+    int32_t *list = nullptr;
+    TC_TRY(tmp.get(&dplus, nn));
+    TC_TRY(tmp.get(&d_max, 1));
+    TC_TRY(tmp.get(&flags, nn));
+    TC_TRY(tmp.get(&list, nn));
+    TC_HIP(hipMemsetAsync(d_max, 0, 4, s));
+    // pass 1: d+ per rank row
+    TC_HIP(hipMemsetAsync(dplus, 0, sizeof(int64_t) * nn, s));
+    k_count_higher<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->rank,
+                                             reinterpret_cast<unsigned long long *>(dplus));
+    TC_LAUNCHED();
+    k_max_i64<<<grid_for(n) < 4096 ? grid_for(n) : 4096, BK, 0, s>>>(n, dplus, d_max);
+    TC_LAUNCHED();
+    uint32_t h_max = 0;
+    TC_HIP(hipMemcpyAsync(&h_max, d_max, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    g->max_dplus = (int32_t)h_max;
+    // TC_ORIENT_SEG_MAX (environment) lowers the LDS-sort limit, so that the
+    // sort-based path can be exercised on small graphs
+    uint32_t seg_max = SEG_MAX;
+    if (const char *ev = getenv("TC_ORIENT_SEG_MAX")) {
+        const long v = strtol(ev, nullptr, 10);
+        if (v >= 0 && v < SEG_MAX) seg_max = (uint32_t)v;
+    }
+    if (h_max > seg_max) {
+        TC_TRY(orient_sorted(g, s));
+        tc_prof_mark(g, 3, s);
+        return TC_OK;
+    }
+    TC_TRY(tc_scan_i64(dplus, g->orp, n, g->orp + n, s));
+    // pass 2
+    k_orient_wave<<<(unsigned)tc_div_up(n, 4), BK, 0, s>>>(n, g->row_ptr, g->col, g->sym2e, g->rank,
+                                                         g->orp, g->ocol, g->o2e, g->orow);
+    TC_LAUNCHED();
+    k_block_rows_flags<<<grid_for(n), BK, 0, s>>>(n, g->row_ptr, g->rank, g->orp, flags);
+    TC_LAUNCHED();
+    int64_t nblk = 0;
+    TC_TRY(compact_vertices(n, flags, list, &nblk, s));
+    if (nblk > 0) {
+        k_orient_block<<<(unsigned)(nblk < 1048576 ? nblk : 1048576), BK, 0, s>>>(
+            list, nblk, g->row_ptr, g->col, g->sym2e, g->rank, g->orp, g->ocol, g->o2e, g->orow);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 3, s);
+    return TC_OK;
+}
 
 // ---------------------------------------------------------------------------
 tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t P,
@@ -310,23 +607,14 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
     return TC_OK;
 }
 
-tc_status tc_orient(tc_graph *g, hipStream_t s) {
+// Orientation by one global sort of the packed (π(low), π(high)) keys; used
+// when some row has more than SEG_MAX higher-ordered neighbours.
+static tc_status orient_sorted(tc_graph *g, hipStream_t s) {
     const int32_t n = g->n;
     const int64_t m = g->m;
     const int bits = g->bits;
     tc_scratch tmp(s);
     int64_t nn = n > 0 ? n : 1;
-    TC_TRY(tc_graph_alloc(g, &g->orp, nn + 1, s));
-    // TC_OCOL_PAD trailing entries let the counting kernels load whole
-    // 32-entry runs without bounds tests (entries past a run are masked)
-    TC_TRY(tc_graph_alloc(g, &g->ocol, m + TC_OCOL_PAD, s));
-    TC_TRY(tc_graph_alloc(g, &g->o2e, m, s));
-    g->max_dplus = 0;
-    if (m == 0) {
-        TC_HIP(hipMemsetAsync(g->orp, 0, sizeof(int64_t) * (nn + 1), s));
-        tc_prof_mark(g, 3, s);
-        return TC_OK;
-    }
     uint64_t *okey = nullptr, *okey2 = nullptr;
     uint32_t *oval2 = nullptr;
     TC_TRY(tmp.get(&okey, m));
@@ -340,7 +628,7 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     if (oval != g->o2e) {
         TC_HIP(hipMemcpyAsync(g->o2e, oval, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
     }
-    k_orient_split<<<grid_for(m), BK, 0, s>>>(m, okey, bits, g->ocol);
+    k_orient_split<<<grid_for(m), BK, 0, s>>>(m, okey, bits, g->ocol, g->orow);
     TC_LAUNCHED();
     uint32_t *rs = nullptr, *re = nullptr, *d_max = nullptr;
     int64_t *dplus = nullptr;
@@ -356,10 +644,5 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     k_run_len64<<<grid_for(n), BK, 0, s>>>(n, rs, re, dplus, d_max);
     TC_LAUNCHED();
     TC_TRY(tc_scan_i64(dplus, g->orp, n, g->orp + n, s));
-    tc_prof_mark(g, 3, s);
-    uint32_t h_max = 0;
-    TC_HIP(hipMemcpyAsync(&h_max, d_max, 4, hipMemcpyDeviceToHost, s));
-    TC_HIP(hipStreamSynchronize(s));
-    g->max_dplus = (int32_t)h_max;
     return TC_OK;
 }

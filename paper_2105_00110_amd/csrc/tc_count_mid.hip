@@ -65,13 +65,12 @@ static inline unsigned grid_for(int64_t n, int block = BK) {
 // ---------------------------------------------------------------------------
 // Transposed orientation
 // ---------------------------------------------------------------------------
-__global__ void k_slot_rows(int32_t n, const int64_t *__restrict__ orp, uint32_t *__restrict__ key,
-                            uint64_t *__restrict__ val, const int32_t *__restrict__ ocol) {
-    GRID_STRIDE(r, n) {
-        for (int64_t k = orp[r]; k < orp[r + 1]; ++k) {
-            key[k] = (uint32_t)ocol[k];
-            val[k] = ((uint64_t)(uint32_t)r << 32) | (uint64_t)k;
-        }
+__global__ void k_slot_keys(int64_t m, const int32_t *__restrict__ orow,
+                            const int32_t *__restrict__ ocol, uint32_t *__restrict__ key,
+                            uint64_t *__restrict__ val) {
+    GRID_STRIDE(k, m) {
+        key[k] = (uint32_t)ocol[k];
+        val[k] = ((uint64_t)(uint32_t)orow[k] << 32) | (uint64_t)k;
     }
 }
 
@@ -646,8 +645,10 @@ tc_status build_items(const tc_graph *g, int lo, int hi, int S, int32_t **item_v
 }  // namespace
 
 // Builds in_ptr / in_pair (the transposed orientation) once per handle.
+static tc_status bit_rows_prepare(tc_graph *g, hipStream_t s);
+
 tc_status tc_mid_prepare(tc_graph *g, hipStream_t s) {
-    if (g->in_pair) return TC_OK;
+    if (g->in_pair) return bit_rows_prepare(g, s);
     const int32_t n = g->n;
     const int64_t m = g->m;
     const int64_t nn = n > 0 ? n : 1;
@@ -664,7 +665,7 @@ tc_status tc_mid_prepare(tc_graph *g, hipStream_t s) {
     TC_TRY(tmp.get(&en, nn));
     TC_TRY(tmp.get(&len, nn));
     val = g->in_pair;
-    k_slot_rows<<<grid_for(n), BK, 0, s>>>(n, g->orp, key, val, g->ocol);
+    k_slot_keys<<<grid_for(m), BK, 0, s>>>(m, g->orow, g->ocol, key, val);
     TC_LAUNCHED();
     uint64_t *vres = val, *vswap = val2;
     TC_TRY(tc_sort_u32_u64(&key, &vres, &key2, &vswap, m, g->bits, s));
@@ -677,7 +678,17 @@ tc_status tc_mid_prepare(tc_graph *g, hipStream_t s) {
     k_in_len<<<grid_for(n), BK, 0, s>>>(n, st, en, len);
     TC_LAUNCHED();
     TC_TRY(tc_scan_i64(len, g->in_ptr, n, g->in_ptr + n, s));
-    // bit matrices: rowbase = exclusive scan of each row's word count
+    return bit_rows_prepare(g, s);
+}
+
+// Bit matrices: rowbase = exclusive scan of each row's word count.
+static tc_status bit_rows_prepare(tc_graph *g, hipStream_t s) {
+    if (g->rowbase) return TC_OK;
+    const int32_t n = g->n;
+    const int64_t nn = n > 0 ? n : 1;
+    tc_scratch tmp(s);
+    int64_t *len = nullptr;
+    TC_TRY(tmp.get(&len, nn));
     TC_TRY(tc_graph_alloc(g, &g->rowbase, nn + 1, s));
     k_row_words<<<grid_for(n), BK, 0, s>>>(n, g->orp, len);
     TC_LAUNCHED();

@@ -120,6 +120,7 @@ struct tc_graph {
     int64_t *orp = nullptr;                         // [n+1]
     int32_t *ocol = nullptr;                        // [m]
     uint32_t *o2e = nullptr;                        // [m] canonical edge of each oriented slot
+    int32_t *orow = nullptr;                        // [m] row (rank) of each oriented slot
     // transposed orientation (middle-pivot counting): pairs grouped by the
     // higher end v, entry = (u << 32) | slot of v in N_H(u)
     int64_t *in_ptr = nullptr;                      // [n+1]
@@ -196,6 +197,17 @@ template <typename T>
 __device__ __forceinline__ T tc_wave_sum(T x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, TC_WAVE);
+    return x;
+}
+
+// Maximum across the 64 lanes of a wavefront.
+template <typename T>
+__device__ __forceinline__ T tc_wave_max(T x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        T y = __shfl_xor(x, off, TC_WAVE);
+        x = y > x ? y : x;
+    }
     return x;
 }
 

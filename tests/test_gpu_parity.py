@@ -252,3 +252,18 @@ def test_batch_equals_single(tclib):
         assert int(res["triG"][gi]) == ref.triG
         np.testing.assert_array_equal(res["num"][a:b], ref.num)
         np.testing.assert_array_equal(res["tc"][a:b].view(np.uint64), ref.tc.view(np.uint64))
+
+
+def test_sort_based_orientation_path(tclib, monkeypatch):
+    # rows with more higher-ordered neighbours than the LDS limit are
+    # oriented by a global sort; lower the limit to run that path here
+    monkeypatch.setenv("TC_ORIENT_SEG_MAX", "8")
+    src, dst, n = gg.rmat(12, 16, seed=31)
+    ks, kd, kn = gg.clique(60)
+    src = np.concatenate([src, ks + n]).astype(np.int32)
+    dst = np.concatenate([dst, kd + n]).astype(np.int32)
+    n = n + kn
+    ref = native.o1_definition(src, dst, n)
+    for t in (None, {"algorithm": 1}, {"algorithm": 2}):
+        _say("sort-based orientation, tuning", t)
+        assert_parity(run_gpu(tclib, src, dst, n, tuning=t), ref)
