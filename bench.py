@@ -12,7 +12,19 @@ per second of step time.
 
 Printed on stdout: ONE JSON line.  Progress goes to stderr.
 
+Beside the headline, the same JSON line carries three more workloads, each
+against the plain one-graph-per-launch form on the same GPU:
+
+* ``batched``: 4096 Barabasi-Albert graphs with planted cliques counted as
+  one batch (one launch per stage for all graphs), in graphs/s;
+* ``er``: Erdos-Renyi G(2000, 0.005), seeds 1..5, in microseconds per graph;
+* ``served``: Poisson arrivals of mixed ER / R-MAT / BA requests (edge
+  counts log-uniform in [1e3, 2e7]) through the serving loop, at 0.5x and
+  0.8x of the closed-loop capacity, with p50/p99 latency and a bit-exact
+  check of every served result against the same request run alone.
+
   python bench.py [--steps K] [--warmup W] [--scale S] [--no-cpu-baseline]
+                  [--no-batched] [--no-serve] [--serve-requests N] [--autotune]
 """
 import argparse
 import hashlib
@@ -44,6 +56,15 @@ def parse():
                     help="JSON file with tc_tuning knobs (default: library defaults, or "
                          "the autotuned file for this device if present)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-er", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the counting knobs on each workload first and store them")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle counts rows v with v %% stride == 0 (0 = automatic)")
     return ap.parse_args()
@@ -96,6 +117,170 @@ def cpu_baseline(src, dst, n, m, stride):
     }
 
 
+def batched_leg(args, stream, autotune):
+    """4096 BA graphs: one batch vs one graph per launch (device-resident pairs)."""
+    import torch
+    from paper_2105_00110_amd import graphgen as gg
+    from paper_2105_00110_amd import tc
+
+    G = args.batch_graphs
+    wl = f"batched_ba{G}"
+    log(f"batched: generating {G} BA graphs (seed 4096)")
+    src, dst, po, vo = gg.batched_ba(G, seed=4096)
+    d_src = torch.from_numpy(src).cuda()
+    d_dst = torch.from_numpy(dst).cuda()
+    torch.cuda.synchronize()
+    tuning = autotune.load(wl)
+    if args.autotune:
+        g = tc.Graph.batch(d_src, d_dst, po, vo, stream=stream)
+        res = autotune.tune(g, log=log)
+        g.close()
+        autotune.store(wl, res, device=torch.cuda.get_device_name(0))
+        tuning = res["tuning"]
+        tc.tc_set_profiling(False)
+
+    m = None
+
+    def bstep():
+        nonlocal m
+        g = tc.Graph.batch(d_src, d_dst, po, vo, stream=stream)
+        g.compute(tuning)
+        if m is None:
+            m = g.m
+        g.close()
+
+    bstep()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bstep()
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / reps
+    log(f"batched: {G} graphs in {ms_batch:.2f} ms per batch")
+
+    def single(gi):
+        a, b = int(po[gi]), int(po[gi + 1])
+        g = tc.Graph.from_edges(d_src[a:b], d_dst[a:b], int(vo[gi + 1] - vo[gi]), stream=stream)
+        g.compute(tuning)
+        g.close()
+
+    for gi in range(min(32, G)):
+        single(gi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gi in range(G):
+        single(gi)
+    torch.cuda.synchronize()
+    ms_single = (time.perf_counter() - t0) * 1e3
+    log(f"batched: one graph per launch {ms_single:.1f} ms for {G} graphs")
+    return {
+        "workload": wl, "graphs": G, "pairs": int(len(src)), "n": int(vo[-1]), "m": int(m),
+        "ms_per_batch": round(ms_batch, 3), "graphs_per_s": G / (ms_batch / 1e3),
+        "edges_per_s": m / (ms_batch / 1e3),
+        "one_graph_per_launch": {"ms": round(ms_single, 3), "graphs_per_s": G / (ms_single / 1e3)},
+        "speedup_vs_one_graph_per_launch": round(ms_single / ms_batch, 2),
+        "tuning": tuning,
+    }
+
+
+def er_leg(stream, reps=20):
+    """G(2000, 0.005), seeds 1..5: latency of one graph per launch, and the
+    five as one batch."""
+    import numpy as np
+    import torch
+    from paper_2105_00110_amd import graphgen as gg
+    from paper_2105_00110_amd import tc
+
+    graphs = [gg.er(2000, 0.005, seed=s) for s in range(1, 6)]
+    dev = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), n) for a, b, n in graphs]
+    torch.cuda.synchronize()
+
+    def one(s, d, n):
+        g = tc.Graph.from_edges(s, d, n, stream=stream)
+        g.compute()
+        g.close()
+
+    for s, d, n in dev:
+        one(s, d, n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for s, d, n in dev:
+            one(s, d, n)
+    torch.cuda.synchronize()
+    us_single = (time.perf_counter() - t0) * 1e6 / (reps * len(dev))
+    src = np.concatenate([g[0] for g in graphs])
+    dst = np.concatenate([g[1] for g in graphs])
+    po = np.zeros(len(graphs) + 1, np.int64)
+    vo = np.zeros(len(graphs) + 1, np.int64)
+    np.cumsum([len(g[0]) for g in graphs], out=po[1:])
+    np.cumsum([g[2] for g in graphs], out=vo[1:])
+    ds, dd = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = tc.Graph.batch(ds, dd, po, vo, stream=stream)
+        g.compute()
+        g.close()
+    torch.cuda.synchronize()
+    us_batch = (time.perf_counter() - t0) * 1e6 / (reps * len(graphs))
+    log(f"er: {us_single:.1f} us per graph alone, {us_batch:.1f} us per graph in a batch of 5")
+    return {"workload": "er_n2000_p0.005_seeds1-5", "us_per_graph": round(us_single, 1),
+            "us_per_graph_batched5": round(us_batch, 1)}
+
+
+def served_leg(args, autotune):
+    """Serving loop at 0.5x and 0.8x of the closed-loop capacity."""
+    import torch
+    from paper_2105_00110_amd import serve
+
+    N = args.serve_requests
+    log(f"served: generating {N} requests (seed 5)")
+    t0 = time.perf_counter()
+    reqs = serve.make_requests(N, seed=5)
+    pairs = sum(r.pairs for r in reqs)
+    log(f"served: generated {pairs} pairs in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.Stream()
+    for r in reqs[:8]:  # warm the path
+        serve.run_alone(r, stream.cuda_stream)
+    torch.cuda.synchronize()
+    secs, alone = serve.closed_loop(reqs, stream.cuda_stream)
+    ref = [serve.digest(a) for a in alone]
+    del alone
+    capacity = N / secs
+    log(f"served: closed loop (one graph per launch, one at a time) {secs:.2f} s, "
+        f"{capacity:.1f} graphs/s")
+    cfg = serve.ServerConfig(budget_bytes=int(args.serve_budget_gb * (1 << 30)),
+                             streams=args.serve_streams)
+    out = {
+        "workload": f"serve_mix_er_rmat_ba_m1e3-2e7_n{N}",
+        "requests": N, "pairs": int(pairs),
+        "budget_gb": args.serve_budget_gb, "streams": args.serve_streams,
+        "small_pairs": cfg.small_pairs, "batch_pairs": cfg.batch_pairs,
+        "closed_loop": {"seconds": round(secs, 3), "graphs_per_s": capacity},
+        "runs": [],
+    }
+    for frac in (0.5, 0.8, None):
+        # None: every request queued at t = 0, the server's own capacity
+        rate = frac * capacity if frac else float("inf")
+        arrivals = serve.poisson_arrivals(N, rate, seed=5) if frac else None
+        srv = serve.Server(cfg)
+        replies = srv.run(reqs, arrivals)
+        ok = [r for r in replies if r.error is None]
+        same = all(serve.digest(r.results) == ref[r.rid] for r in ok)
+        summ = serve.latency_summary(replies)
+        run = {"rate_per_s": round(rate, 2) if frac else "all at t=0",
+               "load": frac if frac else "saturated", **{k: round(v, 3) if isinstance(v, float)
+                                                                else v for k, v in summ.items()},
+               "graphs_per_s": len(ok) / srv.makespan, "makespan_s": round(srv.makespan, 3),
+               "errors": len(replies) - len(ok), "mix_equals_alone": bool(same), **srv.stats}
+        log(f"served at {frac}x capacity: {json.dumps(run)}")
+        out["runs"].append(run)
+        del replies
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -111,15 +296,15 @@ def main():
 
     torch.cuda.set_device(0)
     tc.load()
+    from paper_2105_00110_amd import autotune
+    wl_main = f"rmat_s{args.scale}_ef{args.edge_factor}"
     tuning = None
-    tpath = args.tuning
-    if tpath is None:
-        cand = os.path.join(ROOT, "paper_2105_00110_amd", "tuning", "mi355x.json")
-        if os.path.exists(cand):
-            tpath = cand
-    if tpath:
-        with open(tpath) as f:
+    if args.tuning:
+        with open(args.tuning) as f:
             tuning = json.load(f).get("tuning")
+    elif not args.autotune:
+        tuning = autotune.load(wl_main)
+    if tuning:
         log("tuning", tuning)
 
     log(f"generating R-MAT scale {args.scale}, edge factor {args.edge_factor}, seed {args.seed}")
@@ -130,6 +315,14 @@ def main():
     d_dst = torch.from_numpy(dst).cuda()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream().cuda_stream
+
+    if args.autotune:
+        g = tc.Graph.from_edges(d_src, d_dst, n, stream=stream)
+        res = autotune.tune(g, log=log)
+        g.close()
+        autotune.store(wl_main, res, device=torch.cuda.get_device_name(0))
+        tuning = res["tuning"]
+        log(f"autotuned {wl_main}: {res['ms']} ms (defaults {res['default_ms']} ms)", tuning)
 
     tc.tc_set_profiling(True)
     stage_sum = None
@@ -214,8 +407,17 @@ def main():
         "roofline": roofline,
     }
 
+    del d_src, d_dst
+    torch.cuda.empty_cache()
+    tc.tc_set_profiling(False)
+    if not args.no_batched:
+        result["batched"] = batched_leg(args, stream, autotune)
+    if not args.no_er:
+        result["er"] = er_leg(stream)
+    if not args.no_serve:
+        result["served"] = served_leg(args, autotune)
+
     if not args.no_cpu_baseline:
-        del d_src, d_dst
         stride = args.cpu_stride or max(1, 1 << max(0, args.scale - 20))
         log(f"CPU baseline: oracle O2 with row stride {stride}")
         cb = cpu_baseline(src, dst, n, m, stride)

@@ -383,6 +383,7 @@ tc_status tc_compute_tuned(tc_graph *g, const tc_tuning *tuning, void *stream) {
     g->last_stream = s;
     g->computed = false;
     g->prof_compute = false;
+    g->prof = g_profiling;  // the switch as it stands when this compute starts
     tc_prof_mark(g, 4, s);
     TC_TRY(tc_count(g, tuning, s));
     TC_TRY(tc_aggregate(g, s));

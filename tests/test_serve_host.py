@@ -1,0 +1,117 @@
+"""Host logic of the serving loop and the autotuner (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2105_00110_amd import serve
+
+
+def test_request_specs_mix_and_sizes():
+    specs = serve.request_specs(3000, seed=5)
+    fams = [f for f, _, _ in specs]
+    for f in serve.FAMILIES:
+        assert abs(fams.count(f) / len(fams) - 1 / 3) < 0.04
+    ms = np.array([m for _, m, _ in specs], float)
+    assert ms.min() >= 1e3 and ms.max() <= 2e7
+    # log-uniform: log10 m is uniform on [3, log10 2e7]
+    lo, hi = 3.0, math.log10(2e7)
+    lg = np.log10(ms)
+    assert abs(lg.mean() - (lo + hi) / 2) < 0.1
+    assert [s for _, _, s in specs] == list(range(5, 5 + 3000))
+
+
+def test_request_specs_deterministic():
+    assert serve.request_specs(50, seed=9) == serve.request_specs(50, seed=9)
+
+
+def test_poisson_arrivals():
+    a = serve.poisson_arrivals(20000, rate=250.0, seed=5)
+    assert a[0] == 0.0 and np.all(np.diff(a) >= 0)
+    gaps = np.diff(a)
+    assert abs(gaps.mean() - 1 / 250.0) < 0.05 / 250.0
+    # exponential gaps: coefficient of variation 1
+    assert abs(gaps.std() / gaps.mean() - 1.0) < 0.05
+
+
+@pytest.mark.parametrize("fam", serve.FAMILIES)
+def test_make_graph_sizes(fam):
+    src, dst, n = serve.make_graph(fam, 20000, seed=3)
+    assert src.dtype == np.int32 and dst.dtype == np.int32
+    assert src.min() >= 0 and dst.min() >= 0 and max(src.max(), dst.max()) < n
+    assert 0.5 * 20000 <= len(src) <= 1.5 * 20000
+
+
+class _R:
+    def __init__(self, rid, pairs, n=10):
+        self.rid, self.n = rid, n
+        self.src = np.zeros(pairs, np.int32)
+        self.dst = np.zeros(pairs, np.int32)
+        self.arrival = 0.0
+
+    @property
+    def pairs(self):
+        return self.src.shape[0]
+
+
+def _server(monkeypatch, **cfg):
+    # a server without streams: only the unit former is exercised
+    monkeypatch.setattr(serve, "estimate_bytes", lambda reqs: 100 * sum(r.pairs for r in reqs))
+    s = serve.Server.__new__(serve.Server)
+    s.cfg = serve.ServerConfig(**cfg)
+    return s
+
+
+def test_form_unit_batches_small_in_order(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250)
+    q = [_R(0, 50), _R(1, 90), _R(2, 99), _R(3, 40), _R(4, 500)]
+    u = s._form_unit(q, 10**9)
+    assert [r.rid for r in u.reqs] == [0, 1, 2]  # the next one would pass 250 pairs
+    assert u.bytes == 100 * 239
+
+
+def test_form_unit_large_alone(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250)
+    q = [_R(0, 500), _R(1, 10)]
+    u = s._form_unit(q, 10**9)
+    assert [r.rid for r in u.reqs] == [0]
+
+
+def test_form_unit_waits_and_rejects(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10000, small_pairs=100, batch_pairs=250)
+    assert s._form_unit([_R(0, 90)], 8000) is None         # fits the budget, not what is free
+    assert s._form_unit([_R(0, 101)], 10000) is serve._REJECT  # larger than the whole budget
+    u = s._form_unit([_R(0, 40), _R(1, 50)], 5000)          # the second would exceed free memory
+    assert [r.rid for r in u.reqs] == [0]
+
+
+def test_latency_summary_skips_warmup():
+    reps = [serve.Reply(i, {}, None, arrival=float(i), done=float(i) + (10.0 if i < 5 else 0.001))
+            for i in range(100)]
+    s = serve.latency_summary(reps, warmup_frac=0.05)
+    assert s["measured_requests"] == 95
+    assert abs(s["p99_ms"] - 1.0) < 1e-6 and abs(s["p50_ms"] - 1.0) < 1e-6
+
+
+def test_digest_sensitive_to_every_array():
+    base = {"tri": np.arange(4, dtype=np.uint64), "support": np.arange(3, dtype=np.uint64),
+            "triG": np.array([1], np.uint64), "num": np.arange(4, dtype=np.uint64),
+            "tc": np.linspace(0, 1, 4)}
+    d0 = serve.digest(base)
+    for k in base:
+        other = {kk: vv.copy() for kk, vv in base.items()}
+        other[k] = other[k].copy()
+        other[k].view(np.uint8)[0] ^= 1
+        assert serve.digest(other) != d0
+
+
+def test_autotune_store_load(tmp_path):
+    from paper_2105_00110_amd import autotune
+    p = str(tmp_path / "t.json")
+    assert autotune.load("w", p) is None
+    autotune.store("w", {"tuning": {"item_pairs": 256}, "ms": 1.0, "default_ms": 2.0,
+                         "trials": [1, 2]}, p, device="dev")
+    autotune.store("v", {"tuning": {"item_pairs": 512}, "ms": 1.0, "default_ms": 2.0,
+                         "trials": []}, p)
+    assert autotune.load("w", p) == {"item_pairs": 256}
+    assert autotune.load("v", p) == {"item_pairs": 512}
