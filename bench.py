@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="finish with a device-to-device copy of this many GiB, the known-size "
+                         "kernel that scales rocprofv3's FETCH_SIZE / WRITE_SIZE readings")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the counting knobs on each workload first and store them")
     ap.add_argument("--cpu-stride", type=int, default=0,
@@ -354,6 +357,20 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     stages = {k: v / args.steps for k, v in stage_sum.items()}
+    count_ms = sum(stages[k] for k in ("count_light", "count_heavy", "count_huge", "fold"))
+
+    # the same step from pinned host buffers: pairs cross PCIe inside the step
+    h_src = torch.from_numpy(src).pin_memory()
+    h_dst = torch.from_numpy(dst).pin_memory()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = tc.Graph.from_edges(h_src.numpy(), h_dst.numpy(), n, stream=stream)
+    g.compute(tuning)
+    g.close()
+    torch.cuda.synchronize()
+    pcie_rate = m / (time.perf_counter() - t0)
+    del h_src, h_dst
+    log(f"PCIe-inclusive step: {pcie_rate:.3e} edges/s")
     log("stage ms", json.dumps({k: round(v, 3) for k, v in stages.items()}))
     log("work", json.dumps(work))
 
@@ -366,11 +383,17 @@ def main():
     algo_bytes = 4 * work[f"cand_{b}"] + 8 * work[f"edges_{b}"] + 8 * work[f"rows_{b}"]
     dur_s = stages[dom] / 1e3
     achieved = algo_bytes / dur_s / 1e9 if dur_s > 0 else 0.0
-    digest = source_digest(["tc_count.hip"])
+    digest = source_digest(["tc_count.hip", "tc_count_mid.hip", "tc_table.h", "tc_internal.h"])
     traffic = counter_traffic(dom, digest)
+    kernel_names = {"count_light": "k_mid_wave", "count_heavy": "k_mid_block",
+                    "count_huge": "k_mid_block<true>"}
+    if work.get("algorithm") == 1:
+        kernel_names = {"count_light": "k_count_light", "count_heavy": "k_count_heavy",
+                        "count_huge": "k_count_heavy<true>"}
     roofline = {
         "bound": "hbm",
-        "kernel": dom,
+        "kernel": kernel_names[dom],
+        "stage": dom,
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -405,6 +428,14 @@ def main():
                                                     "count_huge", "tri", "aggregate"]) / 1e3),
         "work": work,
         "roofline": roofline,
+        # the count priced in the low-pivot form, 4 B per candidate of
+        # W_hash = sum over v->u of |N_H(u)|, over the whole count stage
+        "survey_algorithmic_count": {
+            "bytes": 4 * work["w_hash"], "ms": round(count_ms, 3),
+            "GBps": round(4 * work["w_hash"] / (count_ms / 1e3) / 1e9, 1),
+            "frac_of_peak": round(4 * work["w_hash"] / (count_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        },
+        "pcie_inclusive_edges_per_s": pcie_rate,
     }
 
     del d_src, d_dst
@@ -423,6 +454,15 @@ def main():
         cb = cpu_baseline(src, dst, n, m, stride)
         result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         log(f"CPU baseline done: {cb['value']:.3e} edges/s, est. full {cb['est_full_s']:.1f} s")
+    if args.copy_calibration > 0:
+        nbytes = int(args.copy_calibration * (1 << 30))
+        a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(7)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = nbytes
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
     print(json.dumps(result), flush=True)
 
 
