@@ -366,11 +366,24 @@ def main():
     t0 = time.perf_counter()
     g = tc.Graph.from_edges(h_src.numpy(), h_dst.numpy(), n, stream=stream)
     g.compute(tuning)
-    g.close()
     torch.cuda.synchronize()
     pcie_rate = m / (time.perf_counter() - t0)
     del h_src, h_dst
     log(f"PCIe-inclusive step: {pcie_rate:.3e} edges/s")
+
+    # Algorithm 3's algebraic numerator on the same graph, a second device
+    # path: its time, and whether it equals Algorithm 2's numerator
+    alg = torch.empty(n, dtype=torch.int64, device="cuda")
+    tc.tc_numerator_algebraic(g.h, alg.data_ptr(), tc.TC_MEM_DEVICE, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tc.tc_numerator_algebraic(g.h, alg.data_ptr(), tc.TC_MEM_DEVICE, stream)
+    torch.cuda.synchronize()
+    alg_ms = (time.perf_counter() - t0) * 1e3
+    alg_equal = bool(torch.equal(alg, g.results_device()["num"]))
+    g.close()
+    del alg
+    log(f"algebraic numerator: {alg_ms:.2f} ms, equal to Algorithm 2's: {alg_equal}")
     log("stage ms", json.dumps({k: round(v, 3) for k, v in stages.items()}))
     log("work", json.dumps(work))
 
@@ -436,6 +449,8 @@ def main():
             "frac_of_peak": round(4 * work["w_hash"] / (count_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         },
         "pcie_inclusive_edges_per_s": pcie_rate,
+        "algebraic_numerator": {"ms": round(alg_ms, 3), "equals_algorithm2": alg_equal,
+                                "aggregate_ms": round(stages["aggregate"], 3)},
     }
 
     del d_src, d_dst

@@ -194,6 +194,19 @@ tc_status tc_get_edges(const tc_graph *g, int32_t *u, int32_t *v, int32_t mem_ki
 tc_status tc_get_results(const tc_graph *g, uint64_t *tri, uint64_t *support, uint64_t *triG,
                          uint64_t *num, double *tc, int32_t mem_kind, void *stream);
 
+/* Numerator by the algebraic form (Sec. "Algebraic Algorithm", Algorithm 3;
+ * Proposition 2): num = 1/2 (3A - 2T' + I)(T 1), where T = A^2 o A carries the
+ * support of the last tc_compute and T' is its 0/1 pattern, evaluated as two
+ * sparse matrix-vector passes over the symmetric adjacency.  It shares no
+ * kernel with tc_compute's aggregation (Algorithm 2), so num[] here equals
+ * tc_get_results' num[] exactly; tests use it as a cross-check.
+ * num[n] (uint64, vertex order; per batch, concatenated like tri[]).  The
+ * call allocates 4*2m + 16*n bytes of stream-ordered scratch and, with
+ * TC_MEM_HOST, returns after the copy.  TC_ERR_NOT_COMPUTED before
+ * tc_compute; TC_ERR_DEVICE if a product comes out odd (it cannot if the
+ * support is a valid T). */
+tc_status tc_numerator_algebraic(const tc_graph *g, uint64_t *num, int32_t mem_kind, void *stream);
+
 /* Device bytes currently held by the handle. */
 tc_status tc_graph_device_bytes(const tc_graph *g, int64_t *bytes);
 

@@ -28,6 +28,7 @@ HIP_SOURCES = [
     "tc_count.hip",
     "tc_count_mid.hip",
     "tc_aggregate.hip",
+    "tc_algebraic.hip",
     "tc_api.hip",
 ]
 

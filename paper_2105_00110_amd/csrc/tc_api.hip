@@ -413,6 +413,22 @@ tc_status tc_get_edges(const tc_graph *g, int32_t *u, int32_t *v, int32_t mem_ki
     return TC_OK;
 }
 
+tc_status tc_numerator_algebraic(const tc_graph *g, uint64_t *num, int32_t mem_kind, void *stream) {
+    if (!g || !num || !valid_kind(mem_kind)) return TC_ERR_INVALID_ARG;
+    if (!g->computed) return TC_ERR_NOT_COMPUTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (g->n == 0) return TC_OK;
+    tc_scratch tmp(s);
+    uint64_t *dst = num;
+    if (mem_kind == TC_MEM_HOST) TC_TRY(tmp.get(&dst, g->n));
+    TC_TRY(tc_alg_numerator(g, dst, s));
+    if (mem_kind == TC_MEM_HOST) {
+        TC_TRY(copy_out(num, dst, sizeof(uint64_t) * g->n, mem_kind, s));
+        TC_HIP(hipStreamSynchronize(s));
+    }
+    return TC_OK;
+}
+
 tc_status tc_get_results(const tc_graph *g, uint64_t *tri, uint64_t *support, uint64_t *triG,
                          uint64_t *num, double *tc, int32_t mem_kind, void *stream) {
     if (!g || !valid_kind(mem_kind)) return TC_ERR_INVALID_ARG;

@@ -170,6 +170,7 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
 tc_status tc_orient(tc_graph *g, hipStream_t s);
 tc_status tc_count(tc_graph *g, const tc_tuning *t, hipStream_t s);
 tc_status tc_aggregate(tc_graph *g, hipStream_t s);
+tc_status tc_alg_numerator(const tc_graph *g, uint64_t *d_num, hipStream_t s);  // tc_algebraic.hip
 tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s);
 tc_status tc_mid_prepare(tc_graph *g, hipStream_t s);
 tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_entries,

@@ -74,6 +74,7 @@ _SIGS = {
     "tc_num_edges": (_i64, [_vp]),
     "tc_get_edges": (_st, [_vp, _vp, _vp, _i32, _vp]),
     "tc_get_results": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "tc_numerator_algebraic": (_st, [_vp, _vp, _i32, _vp]),
     "tc_graph_device_bytes": (_st, [_vp, ctypes.POINTER(_i64)]),
     "tc_estimate_device_bytes": (_i64, [_i64, _i32]),
     "tc_graph_destroy": (None, [_vp]),
@@ -182,6 +183,11 @@ def tc_get_edges(h, u, v, mem_kind, stream):
 def tc_get_results(h, tri, support, triG, num, tc, mem_kind, stream):
     return _check(load().tc_get_results(h, tri, support, triG, num, tc, int(mem_kind), stream),
                   "tc_get_results")
+
+
+def tc_numerator_algebraic(h, num, mem_kind, stream):
+    return _check(load().tc_numerator_algebraic(h, num, int(mem_kind), stream),
+                  "tc_numerator_algebraic")
 
 
 def tc_graph_device_bytes(h):
@@ -364,6 +370,13 @@ class Graph:
         tc_get_results(self.h, _ptr(out["tri"]), _ptr(out["support"]), _ptr(out["triG"]),
                        _ptr(out["num"]), _ptr(out["tc"]), TC_MEM_DEVICE, self.stream)
         return out
+
+    def numerator_algebraic(self):
+        """num[] by Algorithm 3's algebraic form (host copy)."""
+        n = self.n
+        out = np.empty(max(n, 1), np.uint64)
+        tc_numerator_algebraic(self.h, _ptr(out), TC_MEM_HOST, self.stream)
+        return out[:n]
 
     def stage_ms(self):
         return tc_get_stage_ms(self.h)

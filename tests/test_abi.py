@@ -43,6 +43,7 @@ def test_host_only_calls():
     h = ctypes.c_void_p()
     assert lib.tc_graph_from_edges(None, None, -1, 5, 0, None, ctypes.byref(h)) == tc.TC_ERR_INVALID_ARG
     assert lib.tc_graph_from_edges(None, None, 0, 5, 7, None, ctypes.byref(h)) == tc.TC_ERR_INVALID_ARG
+    assert lib.tc_numerator_algebraic(None, None, 0, None) == tc.TC_ERR_INVALID_ARG
 
 
 def test_no_oracle_in_product():

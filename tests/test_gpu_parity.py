@@ -267,3 +267,56 @@ def test_sort_based_orientation_path(tclib, monkeypatch):
     for t in (None, {"algorithm": 1}, {"algorithm": 2}):
         _say("sort-based orientation, tuning", t)
         assert_parity(run_gpu(tclib, src, dst, n, tuning=t), ref)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3 (algebraic numerator) as a second device path
+# ---------------------------------------------------------------------------
+ALG_CASES = {
+    "K12": lambda: gg.clique(12),
+    "bridge_4x6": lambda: gg.bridge_cliques(4, 6),
+    "ring_5x4": lambda: gg.clique_chain(5, 4, ring=True)[:3],
+    "single_tri": lambda: gg.single_triangle_with_pendants((2, 3, 1)),
+    "er_2000": lambda: gg.er(2000, 0.005, seed=3),
+    "rmat_s11": lambda: gg.rmat(11, 16, seed=5),
+}
+
+
+@pytest.mark.parametrize("name", list(ALG_CASES))
+def test_algebraic_numerator_matches_oracle(tclib, name):
+    from oracle import algebraic
+    src, dst, n = ALG_CASES[name]()
+    _say("algebraic numerator", name, "n", n, "pairs", len(src))
+    g = tclib.Graph.from_edges(torch.as_tensor(np.ascontiguousarray(src, np.int32)).cuda(),
+                               torch.as_tensor(np.ascontiguousarray(dst, np.int32)).cuda(), n)
+    g.compute()
+    alg = g.numerator_algebraic()
+    num = g.results()["num"]
+    g.close()
+    np.testing.assert_array_equal(alg, num)
+    ref = native.o1_definition(src, dst, n)
+    np.testing.assert_array_equal(alg, ref.num)
+    if n <= 2500:  # the dense algebraic oracle (Proposition 2 in float64)
+        np.testing.assert_array_equal(alg, algebraic.algebraic(src, dst, n).num)
+
+
+def test_algebraic_numerator_rmat_s20_and_batch(tclib):
+    src, dst, n = gg.rmat(20, 16, seed=20)
+    _say("algebraic numerator R-MAT s20")
+    g = tclib.Graph.from_edges(torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n)
+    g.compute()
+    np.testing.assert_array_equal(g.numerator_algebraic(), g.results()["num"])
+    g.close()
+    s2, d2, po, vo = gg.batched_ba(64, seed=77)
+    _say("algebraic numerator, batch of 64 BA graphs")
+    b = tclib.Graph.batch(s2, d2, po, vo)
+    b.compute()
+    np.testing.assert_array_equal(b.numerator_algebraic(), b.results()["num"])
+    b.close()
+
+
+def test_algebraic_numerator_before_compute(tclib):
+    g = tclib.Graph.from_edges(*gg.clique(5)[:2], 5)
+    with pytest.raises(tclib.TCError):
+        g.numerator_algebraic()
+    g.close()
