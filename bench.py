@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-er", action="store_true")
+    ap.add_argument("--no-ingest", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -231,6 +232,51 @@ def er_leg(stream, reps=20):
     log(f"er: {us_single:.1f} us per graph alone, {us_batch:.1f} us per graph in a batch of 5")
     return {"workload": "er_n2000_p0.005_seeds1-5", "us_per_graph": round(us_single, 1),
             "us_per_graph_batched5": round(us_batch, 1)}
+
+
+def ingest_leg(stream):
+    """A text edge list with sparse 64-bit ids (R-MAT scale 20 pairs, ids
+    spread over [2^40, 2^40 + 2^20 * 1000003)): host parse, device relabel,
+    then the whole path."""
+    import tempfile
+
+    import torch
+    from paper_2105_00110_amd import graphgen as gg
+    from paper_2105_00110_amd import tc
+
+    s, d, _ = gg.rmat(20, 16, seed=20)
+    fd, path = tempfile.mkstemp(suffix=".txt")
+    os.close(fd)
+    try:
+        gg.write_text(path, gg.sparse_ids(s), gg.sparse_ids(d))
+        size = os.path.getsize(path)
+        tc.read_edge_text(path)  # page the file in once
+        t0 = time.perf_counter()
+        src, dst = tc.read_edge_text(path)
+        t_parse = time.perf_counter() - t0
+        tc.relabel(src[:1000], dst[:1000], stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s32, d32, ids, n = tc.relabel(src, dst, stream)
+        t_relabel = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        g = tc.Graph.from_edges(s32, d32, n, stream=stream)
+        g.compute()
+        m = g.m
+        g.close()
+        torch.cuda.synchronize()
+        t_path = time.perf_counter() - t0
+    finally:
+        os.unlink(path)
+    P = len(src)
+    log(f"ingest: {size / 1e6:.0f} MB parsed in {t_parse * 1e3:.0f} ms, relabel {t_relabel * 1e3:.1f} ms, "
+        f"path {t_path * 1e3:.1f} ms")
+    return {"workload": "text_rmat_s20_sparse64_ids", "bytes": size, "pairs": P, "n": int(n),
+            "m": int(m), "parse_ms": round(t_parse * 1e3, 2),
+            "parse_MBps": round(size / t_parse / 1e6, 1),
+            "relabel_ms_host_buffers": round(t_relabel * 1e3, 2),
+            "path_ms_host_buffers": round(t_path * 1e3, 2),
+            "parse_threads": os.cpu_count()}
 
 
 def served_leg(args, autotune):
@@ -460,6 +506,8 @@ def main():
         result["batched"] = batched_leg(args, stream, autotune)
     if not args.no_er:
         result["er"] = er_leg(stream)
+    if not args.no_ingest:
+        result["ingest"] = ingest_leg(stream)
     if not args.no_serve:
         result["served"] = served_leg(args, autotune)
 

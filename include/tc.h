@@ -66,7 +66,8 @@ typedef enum tc_status {
     TC_ERR_OVERFLOW = -5,       /* a result would not fit its type          */
     TC_ERR_BUDGET = -6,         /* request larger than the caller's budget  */
     TC_ERR_NOT_COMPUTED = -7,   /* results requested before tc_compute()    */
-    TC_ERR_UNSUPPORTED = -8     /* size beyond the library's index types    */
+    TC_ERR_UNSUPPORTED = -8,    /* size beyond the library's index types    */
+    TC_ERR_IO = -9              /* a file cannot be opened, mapped or read  */
 } tc_status;
 
 #define TC_MEM_HOST 0
@@ -218,6 +219,36 @@ int64_t tc_estimate_device_bytes(int64_t num_pairs, int32_t n);
 /* Releases the handle and its device memory (NULL is a no-op).  Waits for
  * work still queued on the handle's last stream. */
 void tc_graph_destroy(tc_graph *g);
+
+/* ------------------------------------------------------------------------
+ * Ingest of text edge lists with arbitrary ids (the paper's inputs are SNAP
+ * graphs relabelled to 1..n without gaps: Sec. "Comparison", Table 6).
+ *
+ * tc_edge_text_read (host only, no GPU): parses `path`, one pair per line,
+ *   two non-negative decimal ids (< 2^63) separated by spaces or tabs;
+ *   further columns are ignored; blank lines and lines starting with '#'
+ *   or '%' are skipped; '\r' before the newline is accepted.  With
+ *   src = dst = NULL it only counts: *num_pairs receives the number of pair
+ *   lines.  Otherwise it fills src[i], dst[i] (int64, caller-owned, capacity
+ *   entries each) in file order and fails with TC_ERR_INVALID_ARG if
+ *   capacity < *num_pairs.  A malformed line gives TC_ERR_INVALID_ARG and
+ *   its 1-based number in *bad_line (may be NULL).  TC_ERR_IO if the file
+ *   cannot be opened or mapped.  nthreads <= 0 uses every hardware thread.
+ *
+ * tc_relabel_ids: maps the 2*num_pairs ids to 0..n-1 by their rank among
+ *   the distinct ids (order-preserving), writes src32/dst32[num_pairs]
+ *   (int32) and, if ids is not NULL, the sorted distinct original ids
+ *   ids[n] (int64; give it 2*num_pairs entries when n is not known).  *n_out
+ *   receives n.  All arrays are host or device memory as mem_kind says;
+ *   the call returns after its work on `stream` has completed.  Negative
+ *   ids give TC_ERR_VERTEX_RANGE; n >= 2^31 or 2*num_pairs >= 2^32 give
+ *   TC_ERR_UNSUPPORTED.
+ * ---------------------------------------------------------------------- */
+tc_status tc_edge_text_read(const char *path, int64_t *src, int64_t *dst, int64_t capacity,
+                            int64_t *num_pairs, int64_t *bad_line, int32_t nthreads);
+tc_status tc_relabel_ids(const int64_t *src, const int64_t *dst, int64_t num_pairs, int32_t *src32,
+                         int32_t *dst32, int64_t *ids, int64_t *n_out, int32_t mem_kind,
+                         void *stream);
 
 /* ------------------------------------------------------------------------
  * Ranking (the "who is most important" question of Sec. "Comparison"):

@@ -29,6 +29,7 @@ HIP_SOURCES = [
     "tc_count_mid.hip",
     "tc_aggregate.hip",
     "tc_algebraic.hip",
+    "tc_ingest.hip",
     "tc_api.hip",
 ]
 

@@ -220,6 +220,7 @@ const char *tc_status_string(int32_t s) {
         case TC_ERR_BUDGET: return "request exceeds the memory budget";
         case TC_ERR_NOT_COMPUTED: return "results requested before tc_compute";
         case TC_ERR_UNSUPPORTED: return "size beyond the library's index types";
+        case TC_ERR_IO: return "file cannot be opened, mapped or read";
         default: return "unknown status";
     }
 }

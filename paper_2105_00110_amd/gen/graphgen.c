@@ -16,6 +16,7 @@
 #include <math.h>
 #include <pthread.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -334,4 +335,44 @@ void tcgen_uniform(double *out, int64_t count, uint64_t seed, uint64_t salt) {
         uint64_t s = stream_state(seed, (uint64_t)k, salt);
         out[k] = sm_unit(&s);
     }
+}
+
+/* Writes pairs as a text edge list, "u v\n" per line in decimal, after a
+ * comment header line.  Returns 0, or -1 if the file cannot be written. */
+int tcgen_write_text(const char *path, const int64_t *src, const int64_t *dst, int64_t num_pairs) {
+    FILE *f = fopen(path, "wb");
+    if (!f) return -1;
+    enum { BUF = 1 << 20 };
+    char *buf = (char *)malloc(BUF + 64);
+    if (!buf) {
+        fclose(f);
+        return -1;
+    }
+    size_t len = (size_t)snprintf(buf, 64, "# %lld pairs\n", (long long)num_pairs);
+    for (int64_t i = 0; i < num_pairs; ++i) {
+        uint64_t x[2] = {(uint64_t)src[i], (uint64_t)dst[i]};
+        for (int k = 0; k < 2; ++k) {
+            char tmp[24];
+            int t = 0;
+            uint64_t v = x[k];
+            do {
+                tmp[t++] = (char)('0' + v % 10);
+                v /= 10;
+            } while (v);
+            while (t) buf[len++] = tmp[--t];
+            buf[len++] = k == 0 ? ' ' : '\n';
+        }
+        if (len > BUF) {
+            if (fwrite(buf, 1, len, f) != len) {
+                free(buf);
+                fclose(f);
+                return -1;
+            }
+            len = 0;
+        }
+    }
+    int r = (len && fwrite(buf, 1, len, f) != len) ? -1 : 0;
+    free(buf);
+    if (fclose(f) != 0) r = -1;
+    return r;
 }

@@ -58,6 +58,8 @@ def _gen_lib():
         L.tcgen_ba_batch.restype = ctypes.c_int
         L.tcgen_uniform.argtypes = [_f64p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64]
         L.tcgen_uniform.restype = None
+        L.tcgen_write_text.argtypes = [ctypes.c_char_p, _i64p, _i64p, ctypes.c_int64]
+        L.tcgen_write_text.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -110,6 +112,24 @@ def ba(n, m_attach, seed=1, cover=0.10, kmin=5, kmax=20):
     got = L.tcgen_ba(src.ctypes.data, dst.ctypes.data, max(cnt, 1), *args)
     assert got == cnt
     return src[:cnt], dst[:cnt], int(n)
+
+
+def write_text(path, src, dst):
+    """Writes int64 pairs as a text edge list ("u v" per line, one '#'
+    header line)."""
+    src = np.ascontiguousarray(src, np.int64)
+    dst = np.ascontiguousarray(dst, np.int64)
+    if _gen_lib().tcgen_write_text(os.fsencode(path), src, dst, src.shape[0]) != 0:
+        raise OSError(f"cannot write {path}")
+
+
+def sparse_ids(ids, seed=1):
+    """An order-preserving injective map of ids 0..N-1 onto sparse 64-bit
+    ids: id -> id * 1000003 + offset + U{0..999} (the gaps make the ids
+    non-contiguous; the map stays increasing)."""
+    ids = np.asarray(ids, np.int64)
+    jitter = np.floor(uniform(int(ids.max()) + 1 if ids.size else 1, seed, 0x1D) * 1000)
+    return ids * 1000003 + (1 << 40) + jitter.astype(np.int64)[ids]
 
 
 def uniform(count, seed, salt):

@@ -27,6 +27,7 @@ TC_ERR_OVERFLOW = -5
 TC_ERR_BUDGET = -6
 TC_ERR_NOT_COMPUTED = -7
 TC_ERR_UNSUPPORTED = -8
+TC_ERR_IO = -9
 
 TC_MEM_HOST = 0
 TC_MEM_DEVICE = 1
@@ -75,6 +76,9 @@ _SIGS = {
     "tc_get_edges": (_st, [_vp, _vp, _vp, _i32, _vp]),
     "tc_get_results": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "tc_numerator_algebraic": (_st, [_vp, _vp, _i32, _vp]),
+    "tc_edge_text_read": (_st, [ctypes.c_char_p, _vp, _vp, _i64, ctypes.POINTER(_i64),
+                                ctypes.POINTER(_i64), _i32]),
+    "tc_relabel_ids": (_st, [_vp, _vp, _i64, _vp, _vp, _vp, ctypes.POINTER(_i64), _i32, _vp]),
     "tc_graph_device_bytes": (_st, [_vp, ctypes.POINTER(_i64)]),
     "tc_estimate_device_bytes": (_i64, [_i64, _i32]),
     "tc_graph_destroy": (None, [_vp]),
@@ -190,6 +194,52 @@ def tc_numerator_algebraic(h, num, mem_kind, stream):
                   "tc_numerator_algebraic")
 
 
+def tc_edge_text_read(path, src=None, dst=None, capacity=0, nthreads=0):
+    """(status, num_pairs, bad_line); fills src/dst (int64 arrays) when given."""
+    np_ = _i64(0)
+    bad = _i64(-1)
+    st = load().tc_edge_text_read(os.fsencode(path), _ptr(src), _ptr(dst), int(capacity),
+                                  ctypes.byref(np_), ctypes.byref(bad), int(nthreads))
+    return int(st), int(np_.value), int(bad.value)
+
+
+def read_edge_text(path, nthreads=0):
+    """Pairs of a text edge list as two int64 arrays (original ids)."""
+    st, P, bad = tc_edge_text_read(path, nthreads=nthreads)
+    if st == TC_ERR_INVALID_ARG and bad > 0:
+        raise TCError(st, f"tc_edge_text_read: {path}: malformed line {bad}")
+    _check(st, "tc_edge_text_read")
+    src = np.empty(max(P, 1), np.int64)
+    dst = np.empty(max(P, 1), np.int64)
+    st, P2, bad = tc_edge_text_read(path, src, dst, src.shape[0], nthreads)
+    _check(st, "tc_edge_text_read")
+    assert P2 == P
+    return src[:P], dst[:P]
+
+
+def tc_relabel_ids(src, dst, num_pairs, src32, dst32, ids, mem_kind, stream):
+    n = _i64(0)
+    _check(load().tc_relabel_ids(src, dst, int(num_pairs), src32, dst32, ids, ctypes.byref(n),
+                                 int(mem_kind), stream), "tc_relabel_ids")
+    return int(n.value)
+
+
+def relabel(src, dst, stream=None):
+    """Order-preserving relabel of int64 ids to 0..n-1 on the device.
+
+    Host arrays in, host arrays out: (src32, dst32, ids, n) where ids[k] is
+    the original id of new vertex k."""
+    src = np.ascontiguousarray(src, np.int64)
+    dst = np.ascontiguousarray(dst, np.int64)
+    P = src.shape[0]
+    s32 = np.empty(max(P, 1), np.int32)
+    d32 = np.empty(max(P, 1), np.int32)
+    ids = np.empty(max(2 * P, 1), np.int64)
+    n = tc_relabel_ids(_ptr(src), _ptr(dst), P, _ptr(s32), _ptr(d32), _ptr(ids), TC_MEM_HOST,
+                       stream)
+    return s32[:P], d32[:P], ids[:n], n
+
+
 def tc_graph_device_bytes(h):
     b = _i64(0)
     _check(load().tc_graph_device_bytes(h, ctypes.byref(b)), "tc_graph_device_bytes")
@@ -286,6 +336,15 @@ class Graph:
         h = tc_graph_from_csr(_ptr(row_ptr), _ptr(col), n, TC_MEM_DEVICE if dev else TC_MEM_HOST,
                               stream)
         return cls(h, stream)
+
+    @classmethod
+    def from_text(cls, path, stream=None, nthreads=0):
+        """Reads a text edge list, relabels its ids to 0..n-1 (order
+        preserving) and builds the graph.  Returns (graph, ids) where ids[k]
+        is the original id of vertex k."""
+        src, dst = read_edge_text(path, nthreads)
+        s32, d32, ids, n = relabel(src, dst, stream)
+        return cls.from_edges(s32, d32, n, stream=stream), ids
 
     @classmethod
     def batch(cls, src, dst, pair_off, vtx_off, stream=None):
