@@ -111,6 +111,12 @@ const char *tc_status_string(int32_t status);
  *   item_pairs       middle pivot only: lower neighbours of one pivot per
  *                    work item of a wavefront (a workgroup item takes this
  *                    many per wavefront); 64..65536, a multiple of 64.
+ *   bitmap_words     middle pivot only: workgroup pivots whose N_H(v)
+ *                    spans at most 32*bitmap_words ranks are looked up in
+ *                    an LDS bitmap of the span (8 bytes per 32 ranks: the
+ *                    bits and the count of entries before them) instead of
+ *                    the hash table; 0 turns the bitmap off, else a power
+ *                    of two, 256..8192.
  * ---------------------------------------------------------------------- */
 #define TC_ALGO_AUTO 0
 #define TC_ALGO_LOW_PIVOT 1
@@ -123,6 +129,7 @@ typedef struct tc_tuning {
     int32_t lds_max_entries;
     int32_t algorithm;
     int32_t item_pairs;
+    int32_t bitmap_words;
 } tc_tuning;
 
 /* Writes the built-in defaults to *t. */

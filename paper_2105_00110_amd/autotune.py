@@ -7,7 +7,8 @@ The knobs (``include/tc.h``):
   workgroup rows;
 * ``item_pairs``: work-item tile, in (pivot, neighbour) pairs;
 * ``heavy_block`` and ``light_block``: workgroup shapes;
-* ``lds_max_entries``: largest LDS table.
+* ``lds_max_entries``: largest LDS table;
+* ``bitmap_words``: LDS bitmap size for workgroup pivots (0 = hash only).
 
 ``tune`` runs a coordinate search on a built graph.  It starts from the
 library defaults (or a given start) and sweeps one knob at a time over its
@@ -32,6 +33,7 @@ SPACE = {
     "heavy_block": [256, 512, 1024],
     "light_block": [128, 256, 512],
     "lds_max_entries": [2048, 4096, 8192],
+    "bitmap_words": [0, 1024, 2048, 4096, 8192],
 }
 
 # stages that the counting knobs change

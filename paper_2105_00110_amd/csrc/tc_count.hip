@@ -263,6 +263,7 @@ tc_status tc_tuning_default(tc_tuning *t) {
     t->lds_max_entries = 4096;
     t->algorithm = TC_ALGO_AUTO;
     t->item_pairs = 512;
+    t->bitmap_words = 4096;
     return TC_OK;
 }
 
@@ -273,7 +274,9 @@ static bool tuning_valid(const tc_tuning *t) {
            t->light_block <= 1024 && t->light_block % 64 == 0 && pow2(t->lds_max_entries) &&
            t->lds_max_entries >= 1024 && t->lds_max_entries <= 16384 && t->algorithm >= 0 &&
            t->algorithm <= 2 && t->item_pairs >= 64 && t->item_pairs <= 65536 &&
-           t->item_pairs % 64 == 0;
+           t->item_pairs % 64 == 0 &&
+           (t->bitmap_words == 0 ||
+            (pow2(t->bitmap_words) && t->bitmap_words >= 256 && t->bitmap_words <= 8192));
 }
 
 tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {

@@ -92,13 +92,21 @@ __global__ void k_in_len(int32_t n, const uint32_t *__restrict__ s, const uint32
 // Work items: pivot v with |N_H(v)| in [lo, hi] and at least one lower
 // neighbour, cut into slices of at most S pairs.
 // ---------------------------------------------------------------------------
+// Items of the pivots with lo <= |N_H(v)| <= hi; span_mode 1 keeps only
+// pivots whose rank span fits a bitmap, 2 only those whose span does not.
 __global__ void k_item_count(int32_t n, const int64_t *__restrict__ orp,
-                             const int64_t *__restrict__ in_ptr, int lo, int hi, int S,
+                             const int32_t *__restrict__ ocol, const int64_t *__restrict__ in_ptr,
+                             int lo, int hi, int S, int span_mode, int64_t span_max,
                              uint32_t *__restrict__ cnt) {
     GRID_STRIDE(v, n) {
         const int64_t d = orp[v + 1] - orp[v];
         const int64_t in = in_ptr[v + 1] - in_ptr[v];
-        cnt[v] = (d >= lo && d <= hi && in > 0) ? (uint32_t)tc_div_up(in, S) : 0u;
+        bool ok = d >= lo && d <= hi && in > 0;
+        if (ok && span_mode != 0) {
+            const int64_t span = (int64_t)ocol[orp[v + 1] - 1] - ocol[orp[v]] + 1;
+            ok = span_mode == 1 ? span <= span_max : span > span_max;
+        }
+        cnt[v] = ok ? (uint32_t)tc_div_up(in, S) : 0u;
     }
 }
 
@@ -115,16 +123,84 @@ __global__ void k_item_write(int32_t n, const uint32_t *__restrict__ cnt,
 }
 
 // ---------------------------------------------------------------------------
+// Lookups of a pivot's row N_H(v) (position of a rank in the row, or -1).
+//   LK_HASH    the LDS hash table (tc_table.h);
+//   LK_GLOBAL  binary search in device memory (rows too long for LDS);
+//   LK_BITMAP  a bitmap over the row's rank span [lo, lo + span) in LDS:
+//              word x holds bits (rank - lo) in [32x, 32x + 32) and the
+//              number of row entries before them; a probe is one 8-byte
+//              read, a bit test and a popcount.
+// ---------------------------------------------------------------------------
+constexpr int LK_HASH = 0, LK_GLOBAL = 1, LK_BITMAP = 2;
+
+struct BitmapRow {
+    const uint2 *bm;  // {bits, entries before this word}
+    uint32_t lo, span;
+};
+
+template <int N>
+__device__ __forceinline__ void bitmap_find_n(const BitmapRow &b, const uint32_t (&key)[N],
+                                              int (&q)[N]) {
+    uint32_t idx[N];
+    uint2 w[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        idx[e] = key[e] - b.lo;  // keys below lo wrap above span
+        const bool in = idx[e] < b.span;
+        w[e] = b.bm[in ? idx[e] >> 5 : 0];
+        idx[e] = in ? idx[e] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const uint32_t sh = idx[e] & 31;
+        const bool hit = idx[e] != 0xFFFFFFFFu && ((w[e].x >> sh) & 1u);
+        const uint32_t below = w[e].x & ((1u << sh) - 1u);
+        q[e] = hit ? (int)(w[e].y + (uint32_t)__popc(below)) : -1;
+    }
+}
+
+// Builds the bitmap of row ocol[vstart, vstart + d) (sorted ranks) with the
+// threads of a workgroup; words beyond the span are not touched.
+__device__ void bitmap_build(uint2 *bm, uint32_t *scan, const int32_t *__restrict__ ocol,
+                             int64_t vstart, int d, uint32_t lo, uint32_t span) {
+    const int nw = (int)((span + 31) >> 5);
+    for (int x = threadIdx.x; x < nw; x += blockDim.x) bm[x] = make_uint2(0u, 0u);
+    __syncthreads();
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+        const uint32_t r = (uint32_t)ocol[vstart + j] - lo;
+        atomicOr(&bm[r >> 5].x, 1u << (r & 31));
+    }
+    __syncthreads();
+    // exclusive prefix of the word popcounts: each thread a contiguous run
+    const int per = (nw + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int x0 = threadIdx.x * per;
+    uint32_t c = 0;
+    for (int x = x0; x < x0 + per && x < nw; ++x) c += (uint32_t)__popc(bm[x].x);
+    const uint32_t incl = tc_wave_incl_scan(c);
+    const int wv = threadIdx.x / TC_WAVE;
+    if (__lane_id() == TC_WAVE - 1) scan[wv] = incl;
+    __syncthreads();
+    uint32_t before = incl - c;
+    for (int q = 0; q < wv; ++q) before += scan[q];
+    for (int x = x0; x < x0 + per && x < nw; ++x) {
+        bm[x].y = before;
+        before += (uint32_t)__popc(bm[x].x);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // One 64-pair group of pivot v (wave-level).  Pairs g0 .. gend-1 (at most
 // 64).  gx/gs/gb/gt: this wavefront's LDS arrays (exclusive scan of word
 // counts, scan starts, bit-row bases, tail lengths).
 // ---------------------------------------------------------------------------
-template <bool GLOBAL_LOOKUP>
+template <int LK>
 __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                                           const int32_t *__restrict__ ocol,
                                           const uint64_t *__restrict__ in_pair,
                                           const int64_t *__restrict__ rowbase, int64_t g0,
-                                          int64_t gend, const RowTable &t, uint32_t hmax,
+                                          int64_t gend, const RowTable &t, const BitmapRow &bmr,
+                                          uint32_t hmax,
                                           uint32_t *lsup, int64_t vstart, int dv, int64_t *gx,
                                           int64_t *gs, int64_t *gb, int32_t *gt,
                                           uint32_t *__restrict__ bits, uint32_t *__restrict__ osup,
@@ -177,10 +253,12 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                 int qc[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) kk[e] = ww[c + e];
-                if constexpr (GLOBAL_LOOKUP) {
+                if constexpr (LK == LK_GLOBAL) {
 #pragma unroll
                     for (int e = 0; e < 8; ++e)
                         qc[e] = kk[e] <= hmax ? row_search(ocol, vstart, dv, kk[e]) : -1;
+                } else if constexpr (LK == LK_BITMAP) {
+                    bitmap_find_n<8>(bmr, kk, qc);
                 } else {
                     table_find_n<8>(t, kk, hmax, qc);
                 }
@@ -188,7 +266,7 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                 for (int e = 0; e < 8; ++e) {
                     const bool hit = qc[e] >= 0;
                     mask |= (hit ? 1u : 0u) << (c + e);
-                    if constexpr (GLOBAL_LOOKUP) {
+                    if constexpr (LK == LK_GLOBAL) {
                         if (hit) atomicAdd(&osup[vstart + qc[e]], 1u);
                     } else {
                         // a miss adds 0 to this lane's spare counter: no branch
@@ -252,8 +330,9 @@ __global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ o
         for (int j = lane; j < d; j += TC_WAVE) table_insert(t, (uint32_t)ocol[vstart + j], j);
         const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
         for (int64_t g0 = first; g0 < pend; g0 += TC_WAVE)
-            mid_group<false>(orp, ocol, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t, hmax,
-                             lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
+            mid_group<LK_HASH>(orp, ocol, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t,
+                               BitmapRow{nullptr, 0, 0}, hmax, lsup, vstart, d, gx, gs, gb, gt,
+                               bits, osup, found);
         for (int j = lane; j < d; j += TC_WAVE) {
             const uint32_t c = lsup[j];
             if (c) atomicAdd(&osup[vstart + j], c);
@@ -263,14 +342,16 @@ __global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ o
     if (lane == 0 && found) atomicAdd(tri_total, found);
 }
 
-static inline size_t mid_block_bytes(int dmax, int wpb, bool global_lookup) {
-    const size_t t = global_lookup ? 0 : table_bytes(dmax) + counter_bytes(dmax);
+static inline size_t mid_block_bytes(int dmax, int wpb, int lk, int bitmap_words) {
+    size_t t = 0;
+    if (lk == LK_HASH) t = table_bytes(dmax) + counter_bytes(dmax);
+    if (lk == LK_BITMAP) t = 8 * (size_t)bitmap_words + counter_bytes(dmax) + 64;
     return t + (size_t)wpb * GROUP_BYTES;
 }
 
-// One workgroup per item; its wavefronts share the pivot's table and take
-// the item's 64-pair groups in turn.
-template <bool GLOBAL_LOOKUP>
+// One workgroup per item; its wavefronts share the pivot's lookup structure
+// and take the item's 64-pair groups in turn.
+template <int LK>
 __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ orp,
                                                     const int32_t *__restrict__ ocol,
                                                     const int64_t *__restrict__ in_ptr,
@@ -280,7 +361,7 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ item_v,
                                                     const uint32_t *__restrict__ item_first,
                                                     int64_t nitems, int dmax, int item_pairs,
-                                                    uint32_t *__restrict__ osup,
+                                                    int bitmap_words, uint32_t *__restrict__ osup,
                                                     unsigned long long *__restrict__ tri_total) {
     extern __shared__ uint4 lds4[];
     const int wpb = blockDim.x / TC_WAVE;
@@ -288,14 +369,20 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
     const int lane = __lane_id();
     char *base = reinterpret_cast<char *>(lds4);
     size_t tpart = 0;
-    uint32_t *keys = nullptr, *lsup = nullptr;
+    uint32_t *keys = nullptr, *lsup = nullptr, *scan = nullptr;
     uint16_t *pos = nullptr;
-    if constexpr (!GLOBAL_LOOKUP) {
+    uint2 *bm = nullptr;
+    if constexpr (LK == LK_HASH) {
         const size_t nbmax = (size_t)1 << bucket_bits(dmax);
         keys = reinterpret_cast<uint32_t *>(base);
         pos = reinterpret_cast<uint16_t *>(base + 16 * nbmax);
         lsup = reinterpret_cast<uint32_t *>(base + table_bytes(dmax));
         tpart = table_bytes(dmax) + counter_bytes(dmax);
+    } else if constexpr (LK == LK_BITMAP) {
+        bm = reinterpret_cast<uint2 *>(base);
+        lsup = reinterpret_cast<uint32_t *>(base + 8 * (size_t)bitmap_words);
+        scan = reinterpret_cast<uint32_t *>(base + 8 * (size_t)bitmap_words + counter_bytes(dmax));
+        tpart = 8 * (size_t)bitmap_words + counter_bytes(dmax) + 64;
     }
     char *grp = base + tpart + (size_t)wv * GROUP_BYTES;
     int64_t *gx = reinterpret_cast<int64_t *>(grp);
@@ -310,7 +397,8 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
         const int64_t vstart = orp[v];
         const int d = (int)(orp[v + 1] - vstart);
         RowTable t{keys, pos, 0};
-        if constexpr (!GLOBAL_LOOKUP) {
+        BitmapRow bmr{bm, 0, 0};
+        if constexpr (LK == LK_HASH) {
             t.bb = bucket_bits(d);
             for (int j = threadIdx.x; j < (4 << t.bb); j += blockDim.x) keys[j] = EMPTY;
             for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
@@ -318,12 +406,17 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
             for (int j = threadIdx.x; j < d; j += blockDim.x)
                 table_insert(t, (uint32_t)ocol[vstart + j], j);
             __syncthreads();
+        } else if constexpr (LK == LK_BITMAP) {
+            bmr.lo = (uint32_t)ocol[vstart];
+            bmr.span = (uint32_t)ocol[vstart + d - 1] - bmr.lo + 1;
+            for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
+            bitmap_build(bm, scan, ocol, vstart, d, bmr.lo, bmr.span);
         }
         const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
         for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE)
-            mid_group<GLOBAL_LOOKUP>(orp, ocol, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t,
-                                     hmax, lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
-        if constexpr (!GLOBAL_LOOKUP) {
+            mid_group<LK>(orp, ocol, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t, bmr, hmax,
+                          lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
+        if constexpr (LK != LK_GLOBAL) {
             __syncthreads();
             for (int j = threadIdx.x; j < d; j += blockDim.x) {
                 const uint32_t c = lsup[j];
@@ -610,23 +703,35 @@ __global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
 __global__ void k_mid_pivots(int32_t n, const int64_t *__restrict__ orp,
                              const int64_t *__restrict__ in_ptr, int light_max, int huge_min,
                              unsigned long long *__restrict__ acc) {
+    // per-thread bin counts, summed over the wavefront: three atomics per
+    // wavefront instead of one per pivot on the same three words
+    unsigned long long c[3] = {0, 0, 0};
     GRID_STRIDE(v, n) {
         const int64_t d = orp[v + 1] - orp[v];
         if (d < 1 || in_ptr[v + 1] == in_ptr[v]) continue;
         const int bin = d <= light_max ? 0 : (d < huge_min ? 1 : 2);
-        atomicAdd(&acc[bin], 1ull);
+        c[0] += bin == 0;
+        c[1] += bin == 1;
+        c[2] += bin == 2;
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const unsigned long long t = tc_wave_sum(c[b]);
+        if (__lane_id() == 0 && t) atomicAdd(&acc[b], t);
     }
 }
 
-tc_status build_items(const tc_graph *g, int lo, int hi, int S, int32_t **item_v,
-                      uint32_t **item_first, int64_t *count, tc_scratch &keep, hipStream_t s) {
+tc_status build_items(const tc_graph *g, int lo, int hi, int S, int span_mode, int64_t span_max,
+                      int32_t **item_v, uint32_t **item_first, int64_t *count, tc_scratch &keep,
+                      hipStream_t s) {
     const int32_t n = g->n;
     tc_scratch tmp(s);
     uint32_t *cnt = nullptr, *off = nullptr, *tot = nullptr;
     TC_TRY(tmp.get(&cnt, n));
     TC_TRY(tmp.get(&off, n));
     TC_TRY(tmp.get(&tot, 1));
-    k_item_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->in_ptr, lo, hi, S, cnt);
+    k_item_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, lo, hi, S, span_mode,
+                                            span_max, cnt);
     TC_LAUNCHED();
     TC_TRY(tc_scan_u32(cnt, off, n, tot, s));
     uint32_t h = 0;
@@ -714,14 +819,23 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     const int wave_pairs = t.item_pairs;
     const int block_pairs = t.item_pairs * wpb_block;
     tc_scratch items(s);
-    int32_t *wv_v = nullptr, *bl_v = nullptr, *hu_v = nullptr;
-    uint32_t *wv_f = nullptr, *bl_f = nullptr, *hu_f = nullptr;
-    int64_t n_wave = 0, n_block = 0, n_huge = 0;
-    TC_TRY(build_items(g, 1, light_max, wave_pairs, &wv_v, &wv_f, &n_wave, items, s));
-    TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, &bl_v, &bl_f, &n_block, items, s));
-    TC_TRY(build_items(g, huge_min, 0x7FFFFFFF, block_pairs, &hu_v, &hu_f, &n_huge, items, s));
+    int32_t *wv_v = nullptr, *bl_v = nullptr, *bm_v = nullptr, *hu_v = nullptr;
+    uint32_t *wv_f = nullptr, *bl_f = nullptr, *bm_f = nullptr, *hu_f = nullptr;
+    int64_t n_wave = 0, n_block = 0, n_bitmap = 0, n_huge = 0;
+    // workgroup pivots whose rank span fits the LDS bitmap use it; the
+    // others hash (or, above huge_min, search device memory)
+    const int bw = t.bitmap_words;
+    const int64_t span_max = 32 * (int64_t)bw;
+    const int split = bw > 0 ? 1 : 0;
+    TC_TRY(build_items(g, 1, light_max, wave_pairs, 0, 0, &wv_v, &wv_f, &n_wave, items, s));
+    if (split)
+        TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, 1, span_max, &bm_v, &bm_f,
+                           &n_bitmap, items, s));
+    TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, &bl_v,
+                       &bl_f, &n_block, items, s));
+    TC_TRY(build_items(g, huge_min, 0x7FFFFFFF, block_pairs, 0, 0, &hu_v, &hu_f, &n_huge, items, s));
     g->n_light = n_wave;
-    g->n_heavy = n_block;
+    g->n_heavy = n_block + n_bitmap;
     g->n_huge = n_huge;
     // pairs whose pivot closes nothing are never scanned: their rows stay 0
     if (g->bit_words > 0) {
@@ -743,22 +857,31 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 6, s);
+    if (n_bitmap > 0) {
+        const int hmax = g->max_dplus < huge_min - 1 ? g->max_dplus : huge_min - 1;
+        const size_t lds = mid_block_bytes(hmax, wpb_block, LK_BITMAP, bw);
+        int64_t blocks = n_bitmap < 1048576 ? n_bitmap : 1048576;
+        k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bm_v, bm_f, n_bitmap,
+            hmax, block_pairs, bw, g->osup, found);
+        TC_LAUNCHED();
+    }
     if (n_block > 0) {
         const int hmax = g->max_dplus < huge_min - 1 ? g->max_dplus : huge_min - 1;
-        const size_t lds = mid_block_bytes(hmax, wpb_block, false);
+        const size_t lds = mid_block_bytes(hmax, wpb_block, LK_HASH, 0);
         int64_t blocks = n_block < 1048576 ? n_block : 1048576;
-        k_mid_block<false><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
+        k_mid_block<LK_HASH><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bl_v, bl_f, n_block, hmax,
-            block_pairs, g->osup, found);
+            block_pairs, 0, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 7, s);
     if (n_huge > 0) {
-        const size_t lds = mid_block_bytes(0, wpb_block, true);
+        const size_t lds = mid_block_bytes(0, wpb_block, LK_GLOBAL, 0);
         int64_t blocks = n_huge < 1048576 ? n_huge : 1048576;
-        k_mid_block<true><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
+        k_mid_block<LK_GLOBAL><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, hu_v, hu_f, n_huge, 0,
-            block_pairs, g->osup, found);
+            block_pairs, 0, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 8, s);

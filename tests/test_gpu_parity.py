@@ -111,8 +111,14 @@ _SCHEDULES = [
     {"light_max_dplus": 16, "heavy_block": 512, "light_block": 128, "lds_max_entries": 1024},
     {"light_max_dplus": 37, "heavy_block": 192, "light_block": 320, "lds_max_entries": 2048},
 ]
-# every schedule under both pivot choices (low = 1, middle = 2)
-TUNINGS = [None] + [dict(sc, algorithm=a) for a in (1, 2) for sc in _SCHEDULES]
+# every schedule under both pivot choices (low = 1, middle = 2), and the
+# middle pivot's workgroup lookup as hash only, as a small bitmap (pivots
+# spanning more than 8192 ranks fall back to the hash) and as a large one
+TUNINGS = [None] + [dict(sc, algorithm=a) for a in (1, 2) for sc in _SCHEDULES] + [
+    {"algorithm": 2, "bitmap_words": 0, "light_max_dplus": 2},
+    {"algorithm": 2, "bitmap_words": 256, "light_max_dplus": 2, "item_pairs": 64},
+    {"algorithm": 2, "bitmap_words": 8192, "light_max_dplus": 16, "heavy_block": 1024},
+]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNINGS)))
