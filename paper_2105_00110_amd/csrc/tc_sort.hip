@@ -25,6 +25,7 @@ constexpr int SORT_BLOCK = 256;
 constexpr int SORT_WAVES = SORT_BLOCK / TC_WAVE;
 constexpr int SORT_ITEMS = 16;
 constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
+static_assert(SORT_BLOCK == RADIX, "one digit per thread in the scatter's digit scans");
 
 struct NoVal {};
 
@@ -56,15 +57,23 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
     const K *__restrict__ kin, const V *__restrict__ vin, K *__restrict__ kout,
     V *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offsets,
     int64_t tiles) {
+    // The tile is first put in digit order in LDS, then written out by
+    // consecutive threads to consecutive positions of each digit's run, so
+    // the global stores coalesce.
     __shared__ uint32_t wcnt[SORT_WAVES][RADIX];
-    __shared__ uint32_t gbase[RADIX];
+    __shared__ uint32_t gbase[RADIX];   // global start of the tile's keys of each digit
+    __shared__ uint32_t lbase[RADIX];   // start of each digit within the tile
+    __shared__ K skey[SORT_TILE];
+    __shared__ V sval[HAS_VAL ? SORT_TILE : 1];
     for (int i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_BLOCK) (&wcnt[0][0])[i] = 0;
     __syncthreads();
 
     const int w = threadIdx.x / TC_WAVE;
     const int lane = __lane_id();
     const uint64_t lt = tc_lanemask_lt();
-    const int64_t wbase = (int64_t)blockIdx.x * SORT_TILE + (int64_t)w * (TC_WAVE * SORT_ITEMS);
+    const int64_t tbase = (int64_t)blockIdx.x * SORT_TILE;
+    const int64_t wbase = tbase + (int64_t)w * (TC_WAVE * SORT_ITEMS);
+    const int tn = (int)((n - tbase) < SORT_TILE ? (n - tbase) : SORT_TILE);
 
     K key[SORT_ITEMS];
     V val[SORT_ITEMS];
@@ -96,7 +105,10 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
         if (last) wcnt[w][d] = prior + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < RADIX; d += SORT_BLOCK) {
+    // per digit: offsets of the waves, the tile total, and the global base
+    uint32_t tot = 0;
+    {
+        const int d = threadIdx.x;  // SORT_BLOCK == RADIX
         uint32_t run = 0;
 #pragma unroll
         for (int q = 0; q < SORT_WAVES; ++q) {
@@ -104,7 +116,18 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
             wcnt[q][d] = run;
             run += c;
         }
+        tot = run;
         gbase[d] = offsets[(int64_t)d * tiles + blockIdx.x];
+    }
+    // exclusive scan of the digit totals over the workgroup (one digit per thread)
+    {
+        const uint32_t incl = tc_wave_incl_scan(tot);
+        __shared__ uint32_t wsum[SORT_WAVES];
+        if (lane == TC_WAVE - 1) wsum[w] = incl;
+        __syncthreads();
+        uint32_t before = incl - tot;
+        for (int q = 0; q < w; ++q) before += wsum[q];
+        lbase[threadIdx.x] = before;
     }
     __syncthreads();
 #pragma unroll
@@ -112,10 +135,18 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
         int64_t i = wbase + it * TC_WAVE + lane;
         if (i < n) {
             uint32_t d = (uint32_t)(key[it] >> shift) & (RADIX - 1);
-            uint32_t pos = gbase[d] + wcnt[w][d] + rnk[it];
-            kout[pos] = key[it];
-            if constexpr (HAS_VAL) vout[pos] = val[it];
+            uint32_t lp = lbase[d] + wcnt[w][d] + rnk[it];
+            skey[lp] = key[it];
+            if constexpr (HAS_VAL) sval[lp] = val[it];
         }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < tn; j += SORT_BLOCK) {
+        const K k = skey[j];
+        const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
+        const uint32_t pos = gbase[d] + (uint32_t)j - lbase[d];
+        kout[pos] = k;
+        if constexpr (HAS_VAL) vout[pos] = sval[j];
     }
 }
 
