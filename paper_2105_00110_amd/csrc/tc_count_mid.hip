@@ -451,26 +451,34 @@ __device__ __forceinline__ void planes_flush(uint32_t (&pl)[6], uint32_t (&cnt)[
     for (int k = 0; k < 6; ++k) pl[k] = 0;
 }
 
+// Rows of at most 64 entries, GL lanes each.  Row and column counts of a
+// row are added into the group's LDS counters (the GL lanes of a group sit
+// in one wavefront, so its LDS operations stay in program order), then
+// added to the support once per slot: no device-memory atomics.
 template <int GL>
 __global__ __launch_bounds__(256) void k_fold(const int32_t *__restrict__ rows, int64_t nrows,
                                               const int64_t *__restrict__ orp,
                                               const int64_t *__restrict__ rowbase,
                                               const uint32_t *__restrict__ bits,
                                               uint32_t *__restrict__ osup) {
+    __shared__ uint32_t acc_all[256 / GL][64];
     const int sub = threadIdx.x % GL;
+    uint32_t *acc = acc_all[threadIdx.x / GL];
     const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GL);
     for (int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL; gi < nrows; gi += groups) {
         const int32_t r = rows[gi];
         const int64_t rs = orp[r];
-        const int64_t d = orp[r + 1] - rs;
+        const int64_t d = orp[r + 1] - rs;  // 2 <= d <= 64
         const int64_t base = rowbase[r];
         const int64_t sd = bit_words(d);
-        for (int64_t i = sub; i < d - 1; i += GL) {
-            const int64_t off = base + sd - bit_words(d - i);
-            const int64_t nw = (d - 1 - i + 31) >> 5;
+        for (int64_t i = sub; i < d; i += GL) {
             uint32_t c = 0;
-            for (int64_t q = 0; q < nw; ++q) c += __popc(bits[off + q]);
-            if (c) atomicAdd(&osup[rs + i], c);
+            if (i < d - 1) {
+                const int64_t off = base + sd - bit_words(d - i);
+                const int64_t nw = (d - 1 - i + 31) >> 5;
+                for (int64_t q = 0; q < nw; ++q) c += __popc(bits[off + q]);
+            }
+            acc[i] = c;
         }
         const int64_t nst = (d + 31) >> 5;
         const int64_t G = nst >= GL ? 1 : GL / nst;
@@ -512,8 +520,12 @@ __global__ __launch_bounds__(256) void k_fold(const int32_t *__restrict__ rows, 
 #pragma unroll
             for (int b = 0; b < 32; ++b) {
                 const int64_t j = 32 * c + b;
-                if (j < d && cnt[b]) atomicAdd(&osup[rs + j], cnt[b]);
+                if (j < d && cnt[b]) atomicAdd(&acc[j], cnt[b]);
             }
+        }
+        for (int64_t j = sub; j < d; j += GL) {
+            const uint32_t v = acc[j];
+            if (v) osup[rs + j] += v;  // the group owns row u's slots here
         }
     }
 }
@@ -527,11 +539,17 @@ __device__ __forceinline__ uint32_t stripe_bits(int64_t o, uint32_t lo, uint32_t
     return sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
 }
 
-// Big rows (|N_H(u)| > 64): one wavefront per row, column sums split into
-// units of (stripe c, 63 consecutive rows) dealt round-robin to the lanes,
-// each unit's 32 counts added into the wavefront's LDS column counters
-// (or, for rows longer than the LDS counters, straight to device memory).
-constexpr int FOLD_RC = 63;  // rows per unit: 6 counter planes hold up to 63
+// Big rows (|N_H(u)| > 64): one wavefront per row u.
+//   row sums:    lane i takes rows i, i + 64, ... (its row's words in order);
+//   column sums: lane c owns stripe c (columns 32c .. 32c + 31) of a group
+//                of 64 stripes and walks the rows in order, so at every row
+//                the wavefront reads consecutive words (coalesced) and each
+//                word is fetched about once; the stripe's 32 columns sum in
+//                6 bit-sliced planes flushed to 32 counters every 63 rows.
+// Both sums land in the wavefront's LDS counters (each counter has one
+// owner at a time: plain adds) and are added to the support once.  Rows
+// longer than the LDS counters add to device memory with atomics instead.
+constexpr int FOLD_RC = 63;  // rows per flush: 6 counter planes hold up to 63
 
 __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ rows, int64_t nrows,
                                                   const int64_t *__restrict__ orp,
@@ -544,54 +562,63 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
     uint32_t *colc = colc_all + (size_t)wv * dcap;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / TC_WAVE);
     for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x / TC_WAVE) + wv; gi < nrows; gi += waves) {
-        const int32_t r = rows[gi];
+        // the list is in rank order and the longest rows rank highest: take
+        // it from the end so they start first instead of forming the tail
+        const int32_t r = rows[nrows - 1 - gi];
         const int64_t rs = orp[r];
         const int64_t d = orp[r + 1] - rs;
         const int64_t base = rowbase[r];
         const int64_t sd = bit_words(d);
         const bool in_lds = d <= dcap;
-        if (in_lds)
-            for (int64_t j = lane; j < d; j += TC_WAVE) colc[j] = 0;
-        for (int64_t i = lane; i < d - 1; i += TC_WAVE) {
-            const int64_t off = base + sd - bit_words(d - i);
-            const int64_t nw = (d - 1 - i + 31) >> 5;
+        // row sums (the last slot has no row: it starts at 0)
+        for (int64_t i = lane; i < d; i += TC_WAVE) {
             uint32_t c = 0;
-            for (int64_t q0 = 0; q0 < nw; q0 += 8) {
-                uint32_t x[8];
+            if (i < d - 1) {
+                const int64_t off = base + sd - bit_words(d - i);
+                const int64_t nw = (d - 1 - i + 31) >> 5;
+                for (int64_t q0 = 0; q0 < nw; q0 += 8) {
+                    uint32_t x[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) x[e] = q0 + e < nw ? bits[off + q0 + e] : 0u;
+                    for (int e = 0; e < 8; ++e) x[e] = q0 + e < nw ? bits[off + q0 + e] : 0u;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) c += __popc(x[e]);
+                    for (int e = 0; e < 8; ++e) c += __popc(x[e]);
+                }
             }
-            if (c) atomicAdd(&osup[rs + i], c);
+            if (in_lds) colc[i] = c;
+            else if (c) atomicAdd(&osup[rs + i], c);
         }
-        // unit u = (stripe u / nch, chunk u % nch); all lanes take units in
-        // lockstep rounds (chunks past a stripe's last row are empty)
+        // column sums: lane (stripe c, row group g) of a group of up to 64
+        // stripes; with fewer stripes than lanes the rows are dealt to
+        // G = 64 / stripes groups (row i to group i mod G), and the lanes of
+        // one group read consecutive words of one row at every step
         const int64_t nst = (d + 31) >> 5;
-        const int64_t nch = (d - 1 + FOLD_RC - 1) / FOLD_RC;
-        for (int64_t u0 = 0; u0 < nst * nch; u0 += TC_WAVE) {
-            const int64_t unit = u0 + lane;
-            if (unit >= nst * nch) continue;
-            const int64_t c = unit / nch, ch = unit % nch;
-            const int64_t nrow = min(d - 1, 32 * c + 31);  // rows reaching stripe c
-            const int64_t i0 = ch * FOLD_RC;
-            const int64_t i1 = min(nrow, i0 + FOLD_RC);
-            if (i0 >= i1) continue;
+        for (int64_t sg = 0; sg < nst; sg += TC_WAVE) {
+            const int64_t ns = min((int64_t)TC_WAVE, nst - sg);
+            const int64_t G = TC_WAVE / ns;
+            const int64_t c = sg + lane % ns;
+            const int64_t g = lane / ns;
+            const bool active = g < G;
+            // rows that reach some stripe of the group: i + 1 <= 32 (sg + ns - 1) + 31
+            const int64_t ilast = min(d - 2, 32 * (sg + ns) - 2);
+            const int64_t steps = (ilast + G) / G;  // rows per group, rounded up
+            uint32_t cnt[32];
+#pragma unroll
+            for (int b = 0; b < 32; ++b) cnt[b] = 0;
             uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
-            // 8 rows at a time: all 16 word loads are issued before use
-            for (int64_t ib = i0; ib < i1; ib += 8) {
+            int fill = 0;
+            for (int64_t tb = 0; tb < steps; tb += 8) {
                 uint32_t lo[8], hi[8];
                 int64_t oo[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int64_t i = ib + e;
+                    const int64_t i = g + G * (tb + e);
+                    const int64_t o = 32 * c - (i + 1);  // row bit of the stripe's column 0
                     lo[e] = 0u;
                     hi[e] = 0u;
-                    oo[e] = 0;
-                    if (i < i1) {
+                    oo[e] = -32;
+                    if (active && i <= ilast && o > -32) {
                         const int64_t off = base + sd - bit_words(d - i);
                         const int64_t nw = (d - 1 - i + 31) >> 5;
-                        const int64_t o = 32 * c - (i + 1);
                         const int64_t q = o < 0 ? 0 : (o >> 5);
                         oo[e] = o;
                         if (q < nw) lo[e] = bits[off + q];
@@ -600,7 +627,7 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
                 }
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    uint32_t carry = stripe_bits(oo[e], lo[e], hi[e]);
+                    uint32_t carry = oo[e] > -32 ? stripe_bits(oo[e], lo[e], hi[e]) : 0u;
 #pragma unroll
                     for (int k = 0; k < 6; ++k) {
                         const uint32_t tk = pl[k] & carry;
@@ -608,23 +635,28 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
                         carry = tk;
                     }
                 }
+                fill += 8;
+                if (fill > FOLD_RC - 8) {
+                    planes_flush(pl, cnt);
+                    fill = 0;
+                }
             }
+            planes_flush(pl, cnt);
+            if (active) {
 #pragma unroll
-            for (int b = 0; b < 32; ++b) {
-                uint32_t v = 0;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) v |= ((pl[k] >> b) & 1u) << k;
-                const int64_t j = 32 * c + b;
-                if (v && j < d) {
-                    if (in_lds) atomicAdd(&colc[j], v);
-                    else atomicAdd(&osup[rs + j], v);
+                for (int b = 0; b < 32; ++b) {
+                    const int64_t j = 32 * c + b;
+                    if (j < d && cnt[b]) {
+                        if (in_lds) atomicAdd(&colc[j], cnt[b]);
+                        else atomicAdd(&osup[rs + j], cnt[b]);
+                    }
                 }
             }
         }
         if (in_lds)
             for (int64_t j = lane; j < d; j += TC_WAVE) {
                 const uint32_t v = colc[j];
-                if (v) atomicAdd(&osup[rs + j], v);
+                if (v) osup[rs + j] += v;  // the wavefront owns row u's slots here
             }
     }
 }

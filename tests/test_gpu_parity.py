@@ -326,3 +326,22 @@ def test_algebraic_numerator_before_compute(tclib):
     with pytest.raises(tclib.TCError):
         g.numerator_algebraic()
     g.close()
+
+
+def test_big_clique_fold_two_stripe_groups(tclib):
+    # K_2100: every row of the orientation up to 2099 entries, so the fold
+    # of the largest rows spans two groups of 64 column stripes; pinned by
+    # Observation 1's closed forms (sup = k-2, tri = C(k-1,2), tc = 1)
+    k = 2100
+    src, dst, n = gg.clique(k)
+    _say("K2100 closed forms")
+    g = tclib.Graph.from_edges(torch.from_numpy(np.ascontiguousarray(src, np.int32)).cuda(),
+                               torch.from_numpy(np.ascontiguousarray(dst, np.int32)).cuda(), n)
+    g.compute()
+    r = g.results()
+    g.close()
+    assert r["support"].shape[0] == k * (k - 1) // 2
+    assert np.all(r["support"] == k - 2)
+    assert np.all(r["tri"] == (k - 1) * (k - 2) // 2)
+    assert int(r["triG"][0]) == k * (k - 1) * (k - 2) // 6
+    assert np.all(r["tc"] == 1.0)
