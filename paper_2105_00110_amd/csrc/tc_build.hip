@@ -201,166 +201,128 @@ __global__ void k_run_len64(int32_t n, const uint32_t *__restrict__ s, const uin
 
 // ---------------------------------------------------------------------------
 // Orientation without a global sort (every row at most SEG_MAX entries):
-//   pass 1  d+ of every rank row, counted over the symmetric rows;
-//   pass 2  each row's higher-ordered neighbours are gathered into LDS,
-//           placed by rank (position = number of smaller keys: the keys of
-//           a row are distinct) and written to ocol/o2e, with the row of
-//           every slot in orow.
+//   pass A  each canonical edge is written once, into a bucket of its
+//           lower-ordered endpoint x: (rank of the other end, edge id) at
+//           tmp[row_ptr[x] + slot], slot from an atomic cursor per vertex
+//           (a bucket never outgrows x's symmetric row, and it receives at
+//           most d+(x) entries, which bounds the contention per cursor);
+//   pass B  d+ = the cursors, scanned into the offsets of the rank rows;
+//           each bucket is put in order by rank in LDS and written to
+//           ocol/o2e, with the row of every slot in orow.
 // ---------------------------------------------------------------------------
 constexpr int SEG_MAX = 4096;
-constexpr int SEG_WAVE = 64;        // rows up to this many entries: one wavefront
-constexpr int64_t SCAN_BIG = 4096;  // symmetric rows longer than this: a workgroup
+constexpr int SEG_WAVE = 64;  // buckets up to this many entries: one wavefront
 
-// d+ of every rank row: each canonical edge adds one to the row of its
-// lower-ordered endpoint.  A row receives at most d+ additions, so the
-// contention per word is bounded by the largest out-degree.
-__global__ void k_count_higher(int64_t m, const int32_t *__restrict__ eu,
+__global__ void k_orient_place(int64_t m, const int32_t *__restrict__ eu,
                                const int32_t *__restrict__ ev, const int32_t *__restrict__ rank,
-                               unsigned long long *__restrict__ dplus) {
+                               const int64_t *__restrict__ row_ptr, uint32_t *__restrict__ cursor,
+                               uint64_t *__restrict__ tbuf) {
     // Canonical edges come sorted by their smaller id, so neighbouring lanes
-    // often add to the same row: each run of equal rows in the wavefront
-    // is added once, by its first lane.
+    // often write to the same bucket: each run of equal buckets in the
+    // wavefront takes its slots with one atomic, by its first lane.
     const int lane = __lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; e0 < m; e0 += stride) {
         const int64_t e = e0 + lane;
         const bool valid = e < m;
-        int32_t t = -1;
+        int32_t x = -1;
+        uint32_t other = 0;
         if (valid) {
-            const int32_t a = rank[eu[e]], b = rank[ev[e]];
-            t = a < b ? a : b;
+            const int32_t u = eu[e], v = ev[e];
+            const int32_t a = rank[u], b = rank[v];
+            x = a < b ? u : v;
+            other = (uint32_t)(a < b ? b : a);
         }
-        const int32_t prev = __shfl_up(t, 1, TC_WAVE);
-        const bool head = valid && (lane == 0 || prev != t);
+        const int32_t prev = __shfl_up(x, 1, TC_WAVE);
+        const bool head = valid && (lane == 0 || prev != x);
         const uint64_t heads = __ballot(head);
         const uint64_t valids = __ballot(valid);
+        uint32_t base = 0;
         if (head) {
             const uint64_t later = heads & ~((2ull << lane) - 1);  // heads above this lane
             const int end = later ? __ffsll((long long)later) - 1 : 64 - __clzll((long long)valids);
-            atomicAdd(&dplus[t], (unsigned long long)(end - lane));
+            base = atomicAdd(&cursor[x], (uint32_t)(end - lane));
+        }
+        // the head of this lane's run: the highest head at or below the lane
+        const uint64_t mine = heads & ((2ull << lane) - 1);
+        const int hl = mine ? 63 - __clzll((long long)mine) : 0;
+        base = __shfl(base, hl, TC_WAVE);
+        if (valid) {
+            // one 8-byte store per entry: (rank of the other end << 32) | edge
+            tbuf[row_ptr[x] + base + (uint32_t)(lane - hl)] = ((uint64_t)other << 32) | (uint32_t)e;
         }
     }
 }
 
-__global__ void k_max_i64(int32_t n, const int64_t *__restrict__ v, uint32_t *__restrict__ dmax) {
+// d+ by rank row, and its maximum.
+__global__ void k_dplus_by_rank(int32_t n, const uint32_t *__restrict__ cursor,
+                                const int32_t *__restrict__ rank, int64_t *__restrict__ dplus,
+                                uint32_t *__restrict__ dmax) {
     uint32_t mx = 0;
     GRID_STRIDE(x, n) {
-        const uint32_t d = (uint32_t)v[x];
+        const uint32_t d = cursor[x];
+        dplus[rank[x]] = d;
         mx = d > mx ? d : mx;
     }
     mx = tc_wave_max(mx);
     if (__lane_id() == 0 && mx) atomicMax(dmax, mx);
 }
 
-// Gathers the higher-ordered neighbours of vertex x into LDS (keys = ranks,
-// values = canonical edge ids), places them by rank and writes row rank(x).
-// GL lanes (a wavefront or a workgroup) handle the row; buf holds up to cap
-// entries.
-template <int GL>
-__device__ __forceinline__ void orient_row(int32_t x, const int64_t *__restrict__ row_ptr,
-                                           const int32_t *__restrict__ col,
-                                           const uint32_t *__restrict__ sym2e,
-                                           const int32_t *__restrict__ rank,
-                                           const int64_t *__restrict__ orp,
-                                           int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
-                                           int32_t *__restrict__ orow, uint32_t *bkey,
-                                           uint32_t *bval, uint32_t *fill, int tid) {
-    const int32_t rx = rank[x];
-    const int64_t ob = orp[rx];
-    const int d = (int)(orp[rx + 1] - ob);
-    if (d == 0) return;
-    const int64_t b = row_ptr[x], e = row_ptr[x + 1];
-    for (int64_t p0 = b; p0 < e; p0 += GL) {
-        const int64_t p = p0 + tid;
-        uint32_t ry = 0, ed = 0;
-        bool keep = false;
-        if (p < e) {
-            ry = (uint32_t)rank[col[p]];
-            keep = ry > (uint32_t)rx;
-            ed = sym2e[p];
-        }
-        const uint64_t bal = __ballot(keep);
-        const uint32_t before = (uint32_t)__popcll(bal & tc_lanemask_lt());
-        uint32_t base = 0;
-        if (__lane_id() == 0 && bal) base = atomicAdd(fill, (uint32_t)__popcll(bal));
-        base = __shfl(base, 0, TC_WAVE);
-        if (keep) {
-            bkey[base + before] = ry;
-            bval[base + before] = ed;
-        }
-    }
-    if (GL > TC_WAVE) __syncthreads();
-    for (int i = tid; i < d; i += GL) {
-        const uint32_t key = bkey[i];
-        int pos = 0;
-        for (int j = 0; j < d; ++j) pos += bkey[j] < key ? 1 : 0;
-        const int64_t k = ob + pos;
-        ocol[k] = (int32_t)key;
-        o2e[k] = bval[i];
-        orow[k] = rx;
-    }
-}
-
-// One wavefront per vertex whose row is short and has at most SEG_WAVE
-// higher-ordered neighbours.
+// One wavefront per vertex whose bucket holds 1..SEG_WAVE entries: each
+// lane places its entry by the number of smaller keys (keys of a bucket are
+// distinct ranks).
 __global__ __launch_bounds__(256) void k_orient_wave(
-    int32_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-    const uint32_t *__restrict__ sym2e, const int32_t *__restrict__ rank,
-    const int64_t *__restrict__ orp, int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
+    int32_t n, const int64_t *__restrict__ row_ptr, const uint32_t *__restrict__ cursor,
+    const int32_t *__restrict__ rank, const int64_t *__restrict__ orp,
+    const uint64_t *__restrict__ tbuf, int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
     int32_t *__restrict__ orow) {
-    __shared__ uint32_t sk[4][SEG_WAVE], sv[4][SEG_WAVE], sf[4];
+    __shared__ uint32_t sk[4][SEG_WAVE];
     const int wv = threadIdx.x / TC_WAVE;
+    const int lane = __lane_id();
     const int64_t waves = (int64_t)gridDim.x * 4;
     for (int64_t x = (int64_t)blockIdx.x * 4 + wv; x < n; x += waves) {
-        const int32_t rx = rank[x];
-        const int64_t d = orp[rx + 1] - orp[rx];
-        if (d == 0 || d > SEG_WAVE || row_ptr[x + 1] - row_ptr[x] > SCAN_BIG) continue;
-        if (__lane_id() == 0) sf[wv] = 0;
-        orient_row<TC_WAVE>((int32_t)x, row_ptr, col, sym2e, rank, orp, ocol, o2e, orow, sk[wv],
-                            sv[wv], &sf[wv], __lane_id());
+        const int d = (int)cursor[x];
+        if (d == 0 || d > SEG_WAVE) continue;
+        const int64_t b = row_ptr[x];
+        uint32_t key = 0xFFFFFFFFu, val = 0;
+        if (lane < d) {
+            const uint64_t w = tbuf[b + lane];
+            key = (uint32_t)(w >> 32);
+            val = (uint32_t)w;
+        }
+        sk[wv][lane] = key;
+        int pos = 0;
+        for (int j = 0; j < d; ++j) pos += sk[wv][j] < key ? 1 : 0;
+        if (lane < d) {
+            const int32_t rx = rank[x];
+            const int64_t k = orp[rx] + pos;
+            ocol[k] = (int32_t)key;
+            o2e[k] = val;
+            orow[k] = rx;
+        }
     }
 }
 
-// One workgroup per listed vertex (many higher neighbours or a long row).
-// The row is gathered as packed (rank << 32 | edge) words, padded with
-// all-ones words to a power of two and put in order by a bitonic sort in
-// LDS: log2(P)(log2(P)+1)/2 compare-exchange rounds instead of the
-// quadratic placement, which costs d^2 / 256 reads per thread on long rows.
+// One workgroup per listed vertex (more than SEG_MID entries): the bucket
+// as packed (rank << 32 | edge) words, padded with all-ones words to a power
+// of two, is put in order by a bitonic sort in LDS.
 __global__ __launch_bounds__(256) void k_orient_block(
     const int32_t *__restrict__ list, int64_t nlist, const int64_t *__restrict__ row_ptr,
-    const int32_t *__restrict__ col, const uint32_t *__restrict__ sym2e,
-    const int32_t *__restrict__ rank, const int64_t *__restrict__ orp, int32_t *__restrict__ ocol,
-    uint32_t *__restrict__ o2e, int32_t *__restrict__ orow) {
+    const uint32_t *__restrict__ cursor, const int32_t *__restrict__ rank,
+    const int64_t *__restrict__ orp, const uint64_t *__restrict__ tbuf,
+    int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e, int32_t *__restrict__ orow) {
     __shared__ uint64_t sk[SEG_MAX];
-    __shared__ uint32_t sf;
     const int tid = threadIdx.x;
     for (int64_t i = blockIdx.x; i < nlist; i += gridDim.x) {
         const int32_t x = list[i];
         const int32_t rx = rank[x];
         const int64_t ob = orp[rx];
-        const int d = (int)(orp[rx + 1] - ob);
-        if (tid == 0) sf = 0;
-        __syncthreads();
-        const int64_t b = row_ptr[x], e = row_ptr[x + 1];
-        for (int64_t p0 = b; p0 < e; p0 += 256) {
-            const int64_t p = p0 + tid;
-            uint64_t w = 0;
-            bool keep = false;
-            if (p < e) {
-                const uint32_t ry = (uint32_t)rank[col[p]];
-                keep = ry > (uint32_t)rx;
-                w = ((uint64_t)ry << 32) | sym2e[p];
-            }
-            const uint64_t bal = __ballot(keep);
-            const uint32_t before = (uint32_t)__popcll(bal & tc_lanemask_lt());
-            uint32_t base = 0;
-            if (__lane_id() == 0 && bal) base = atomicAdd(&sf, (uint32_t)__popcll(bal));
-            base = __shfl(base, 0, TC_WAVE);
-            if (keep) sk[base + before] = w;
-        }
+        const int d = (int)cursor[x];
+        const int64_t b = row_ptr[x];
         int P = 1;
         while (P < d) P <<= 1;
-        for (int j = d + tid; j < P; j += 256) sk[j] = ~0ull;
+        for (int j = tid; j < P; j += 256)
+            sk[j] = j < d ? tbuf[b + j] : ~0ull;
         __syncthreads();
         for (int k = 2; k <= P; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
@@ -387,14 +349,58 @@ __global__ __launch_bounds__(256) void k_orient_block(
     }
 }
 
-__global__ void k_block_rows_flags(int32_t n, const int64_t *__restrict__ row_ptr,
-                                   const int32_t *__restrict__ rank,
-                                   const int64_t *__restrict__ orp, uint32_t *__restrict__ f) {
-    GRID_STRIDE(x, n) {
+// One wavefront per listed vertex with SEG_WAVE < entries <= SEG_MID: the
+// same bitonic sort over an LDS buffer of the wavefront's own, so its rounds
+// need no workgroup barrier (a wavefront's LDS operations stay in order).
+constexpr int SEG_MID = 1024;
+
+__global__ __launch_bounds__(256) void k_orient_mid(
+    const int32_t *__restrict__ list, int64_t nlist, const int64_t *__restrict__ row_ptr,
+    const uint32_t *__restrict__ cursor, const int32_t *__restrict__ rank,
+    const int64_t *__restrict__ orp, const uint64_t *__restrict__ tbuf,
+    int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e, int32_t *__restrict__ orow) {
+    __shared__ uint64_t sk_all[4][SEG_MID];
+    const int wv = threadIdx.x / TC_WAVE;
+    const int lane = __lane_id();
+    uint64_t *sk = sk_all[wv];
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < nlist; i += waves) {
+        const int32_t x = list[i];
         const int32_t rx = rank[x];
-        const int64_t d = orp[rx + 1] - orp[rx];
-        f[x] = (d > 0 && (d > SEG_WAVE || row_ptr[x + 1] - row_ptr[x] > SCAN_BIG)) ? 1u : 0u;
+        const int64_t ob = orp[rx];
+        const int d = (int)cursor[x];
+        const int64_t b = row_ptr[x];
+        int P = 1;
+        while (P < d) P <<= 1;
+        for (int j = lane; j < P; j += TC_WAVE) sk[j] = j < d ? tbuf[b + j] : ~0ull;
+        __builtin_amdgcn_wave_barrier();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < (P >> 1); t += TC_WAVE) {
+                    const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                    const uint64_t va = sk[a], vb = sk[a + j];
+                    const bool up = (a & k) == 0;
+                    if ((va > vb) == up) {
+                        sk[a] = vb;
+                        sk[a + j] = va;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        for (int t = lane; t < d; t += TC_WAVE) {
+            const uint64_t w = sk[t];
+            ocol[ob + t] = (int32_t)(w >> 32);
+            o2e[ob + t] = (uint32_t)w;
+            orow[ob + t] = rx;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
+}
+
+__global__ void k_size_flags(int32_t n, const uint32_t *__restrict__ cursor, uint32_t lo,
+                             uint32_t hi, uint32_t *__restrict__ f) {
+    GRID_STRIDE(x, n) f[x] = (cursor[x] > lo && cursor[x] <= hi) ? 1u : 0u;
 }
 
 __global__ void k_compact_flags(int32_t n, const uint32_t *__restrict__ f,
@@ -441,19 +447,20 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     }
     tc_scratch tmp(s);
     int64_t *dplus = nullptr;
-    uint32_t *d_max = nullptr, *flags = nullptr;
+    uint32_t *d_max = nullptr, *flags = nullptr, *cursor = nullptr;
+    uint64_t *tbuf = nullptr;
     int32_t *list = nullptr;
+    TC_TRY(tmp.get(&cursor, nn));
+    TC_TRY(tmp.get(&tbuf, 2 * m));
     TC_TRY(tmp.get(&dplus, nn));
     TC_TRY(tmp.get(&d_max, 1));
-    TC_TRY(tmp.get(&flags, nn));
-    TC_TRY(tmp.get(&list, nn));
     TC_HIP(hipMemsetAsync(d_max, 0, 4, s));
-    // pass 1: d+ per rank row
-    TC_HIP(hipMemsetAsync(dplus, 0, sizeof(int64_t) * nn, s));
-    k_count_higher<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->rank,
-                                             reinterpret_cast<unsigned long long *>(dplus));
+    TC_HIP(hipMemsetAsync(cursor, 0, sizeof(uint32_t) * nn, s));
+    // pass A: buckets of the lower-ordered endpoints
+    k_orient_place<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->rank, g->row_ptr, cursor, tbuf);
     TC_LAUNCHED();
-    k_max_i64<<<grid_for(n) < 4096 ? grid_for(n) : 4096, BK, 0, s>>>(n, dplus, d_max);
+    k_dplus_by_rank<<<grid_for(n) < 4096 ? grid_for(n) : 4096, BK, 0, s>>>(n, cursor, g->rank, dplus,
+                                                                          d_max);
     TC_LAUNCHED();
     uint32_t h_max = 0;
     TC_HIP(hipMemcpyAsync(&h_max, d_max, 4, hipMemcpyDeviceToHost, s));
@@ -472,17 +479,32 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
         return TC_OK;
     }
     TC_TRY(tc_scan_i64(dplus, g->orp, n, g->orp + n, s));
-    // pass 2
-    k_orient_wave<<<(unsigned)tc_div_up(n, 4), BK, 0, s>>>(n, g->row_ptr, g->col, g->sym2e, g->rank,
-                                                         g->orp, g->ocol, g->o2e, g->orow);
+    // pass B: each bucket in rank order
+    k_orient_wave<<<(unsigned)tc_div_up(n, 4), BK, 0, s>>>(n, g->row_ptr, cursor, g->rank, g->orp,
+                                                         tbuf, g->ocol, g->o2e, g->orow);
     TC_LAUNCHED();
-    k_block_rows_flags<<<grid_for(n), BK, 0, s>>>(n, g->row_ptr, g->rank, g->orp, flags);
+    TC_TRY(tmp.get(&flags, nn));
+    TC_TRY(tmp.get(&list, nn));
+    k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_WAVE, SEG_MID, flags);
+    TC_LAUNCHED();
+    int64_t nmid = 0;
+    TC_TRY(compact_vertices(n, flags, list, &nmid, s));
+    if (nmid > 0) {
+        const int64_t blocks = tc_div_up(nmid, 4);
+        k_orient_mid<<<(unsigned)(blocks < 1048576 ? blocks : 1048576), BK, 0, s>>>(
+            list, nmid, g->row_ptr, cursor, g->rank, g->orp, tbuf, g->ocol, g->o2e, g->orow);
+        TC_LAUNCHED();
+    }
+    int32_t *list2 = nullptr;
+    TC_TRY(tmp.get(&list2, nn));
+    k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_MID, 0xFFFFFFFFu, flags);
     TC_LAUNCHED();
     int64_t nblk = 0;
-    TC_TRY(compact_vertices(n, flags, list, &nblk, s));
+    TC_TRY(compact_vertices(n, flags, list2, &nblk, s));
+    list = list2;
     if (nblk > 0) {
         k_orient_block<<<(unsigned)(nblk < 1048576 ? nblk : 1048576), BK, 0, s>>>(
-            list, nblk, g->row_ptr, g->col, g->sym2e, g->rank, g->orp, g->ocol, g->o2e, g->orow);
+            list, nblk, g->row_ptr, cursor, g->rank, g->orp, tbuf, g->ocol, g->o2e, g->orow);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 3, s);
