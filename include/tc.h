@@ -117,6 +117,11 @@ const char *tc_status_string(int32_t status);
  *                    bits and the count of entries before them) instead of
  *                    the hash table; 0 turns the bitmap off, else a power
  *                    of two, 256..8192.
+ *   light_bitmap_pairs  middle pivot only: wavefront pivots (|N_H(v)| <=
+ *                    light_max_dplus) with at least this many lower
+ *                    neighbours and a span that fits the bitmap are
+ *                    counted by the workgroup bitmap kernel instead;
+ *                    0 keeps all of them on the wavefront kernel.
  * ---------------------------------------------------------------------- */
 #define TC_ALGO_AUTO 0
 #define TC_ALGO_LOW_PIVOT 1
@@ -130,6 +135,7 @@ typedef struct tc_tuning {
     int32_t algorithm;
     int32_t item_pairs;
     int32_t bitmap_words;
+    int32_t light_bitmap_pairs;
 } tc_tuning;
 
 /* Writes the built-in defaults to *t. */

@@ -8,7 +8,9 @@ The knobs (``include/tc.h``):
 * ``item_pairs``: work-item tile, in (pivot, neighbour) pairs;
 * ``heavy_block`` and ``light_block``: workgroup shapes;
 * ``lds_max_entries``: largest LDS table;
-* ``bitmap_words``: LDS bitmap size for workgroup pivots (0 = hash only).
+* ``bitmap_words``: LDS bitmap size for workgroup pivots (0 = hash only);
+* ``light_bitmap_pairs``: pair count from which wavefront pivots move to the
+  bitmap kernel (0 = never).
 
 ``tune`` runs a coordinate search on a built graph.  It starts from the
 library defaults (or a given start) and sweeps one knob at a time over its
@@ -34,6 +36,7 @@ SPACE = {
     "light_block": [128, 256, 512],
     "lds_max_entries": [2048, 4096, 8192],
     "bitmap_words": [0, 1024, 2048, 4096, 8192],
+    "light_bitmap_pairs": [0, 16, 64, 256, 1024],
 }
 
 # stages that the counting knobs change

@@ -264,6 +264,7 @@ tc_status tc_tuning_default(tc_tuning *t) {
     t->algorithm = TC_ALGO_AUTO;
     t->item_pairs = 512;
     t->bitmap_words = 4096;
+    t->light_bitmap_pairs = 64;
     return TC_OK;
 }
 
@@ -276,7 +277,8 @@ static bool tuning_valid(const tc_tuning *t) {
            t->algorithm <= 2 && t->item_pairs >= 64 && t->item_pairs <= 65536 &&
            t->item_pairs % 64 == 0 &&
            (t->bitmap_words == 0 ||
-            (pow2(t->bitmap_words) && t->bitmap_words >= 256 && t->bitmap_words <= 8192));
+            (pow2(t->bitmap_words) && t->bitmap_words >= 256 && t->bitmap_words <= 8192)) &&
+           t->light_bitmap_pairs >= 0;
 }
 
 tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {

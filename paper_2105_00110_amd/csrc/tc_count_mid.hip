@@ -92,19 +92,21 @@ __global__ void k_in_len(int32_t n, const uint32_t *__restrict__ s, const uint32
 // Work items: pivot v with |N_H(v)| in [lo, hi] and at least one lower
 // neighbour, cut into slices of at most S pairs.
 // ---------------------------------------------------------------------------
-// Items of the pivots with lo <= |N_H(v)| <= hi; span_mode 1 keeps only
-// pivots whose rank span fits a bitmap, 2 only those whose span does not.
+// Items of the pivots with lo <= |N_H(v)| <= hi.  A pivot "fits the bitmap"
+// when its rank span is at most span_max and it has at least pairs_min
+// pairs; sel 1 keeps only such pivots, sel 2 only the others, sel 0 all.
 __global__ void k_item_count(int32_t n, const int64_t *__restrict__ orp,
                              const int32_t *__restrict__ ocol, const int64_t *__restrict__ in_ptr,
-                             int lo, int hi, int S, int span_mode, int64_t span_max,
+                             int lo, int hi, int S, int sel, int64_t span_max, int64_t pairs_min,
                              uint32_t *__restrict__ cnt) {
     GRID_STRIDE(v, n) {
         const int64_t d = orp[v + 1] - orp[v];
         const int64_t in = in_ptr[v + 1] - in_ptr[v];
         bool ok = d >= lo && d <= hi && in > 0;
-        if (ok && span_mode != 0) {
+        if (ok && sel != 0) {
             const int64_t span = (int64_t)ocol[orp[v + 1] - 1] - ocol[orp[v]] + 1;
-            ok = span_mode == 1 ? span <= span_max : span > span_max;
+            const bool fits = span <= span_max && in >= pairs_min;
+            ok = sel == 1 ? fits : !fits;
         }
         cnt[v] = ok ? (uint32_t)tc_div_up(in, S) : 0u;
     }
@@ -753,17 +755,17 @@ __global__ void k_mid_pivots(int32_t n, const int64_t *__restrict__ orp,
     }
 }
 
-tc_status build_items(const tc_graph *g, int lo, int hi, int S, int span_mode, int64_t span_max,
-                      int32_t **item_v, uint32_t **item_first, int64_t *count, tc_scratch &keep,
-                      hipStream_t s) {
+tc_status build_items(const tc_graph *g, int lo, int hi, int S, int sel, int64_t span_max,
+                      int64_t pairs_min, int32_t **item_v, uint32_t **item_first, int64_t *count,
+                      tc_scratch &keep, hipStream_t s) {
     const int32_t n = g->n;
     tc_scratch tmp(s);
     uint32_t *cnt = nullptr, *off = nullptr, *tot = nullptr;
     TC_TRY(tmp.get(&cnt, n));
     TC_TRY(tmp.get(&off, n));
     TC_TRY(tmp.get(&tot, 1));
-    k_item_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, lo, hi, S, span_mode,
-                                            span_max, cnt);
+    k_item_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, lo, hi, S, sel,
+                                            span_max, pairs_min, cnt);
     TC_LAUNCHED();
     TC_TRY(tc_scan_u32(cnt, off, n, tot, s));
     uint32_t h = 0;
@@ -855,18 +857,29 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     uint32_t *wv_f = nullptr, *bl_f = nullptr, *bm_f = nullptr, *hu_f = nullptr;
     int64_t n_wave = 0, n_block = 0, n_bitmap = 0, n_huge = 0;
     // workgroup pivots whose rank span fits the LDS bitmap use it; the
-    // others hash (or, above huge_min, search device memory)
+    // others hash (or, above huge_min, search device memory).  Wavefront
+    // pivots with at least light_bitmap_pairs pairs and a span that fits go
+    // to the bitmap kernel too (enough pairs to pay for building it).
     const int bw = t.bitmap_words;
     const int64_t span_max = 32 * (int64_t)bw;
     const int split = bw > 0 ? 1 : 0;
-    TC_TRY(build_items(g, 1, light_max, wave_pairs, 0, 0, &wv_v, &wv_f, &n_wave, items, s));
+    const int lsplit = (bw > 0 && t.light_bitmap_pairs > 0) ? 1 : 0;
+    int32_t *lb_v = nullptr;
+    uint32_t *lb_f = nullptr;
+    int64_t n_lbitmap = 0;
+    TC_TRY(build_items(g, 1, light_max, wave_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs,
+                       &wv_v, &wv_f, &n_wave, items, s));
+    if (lsplit)
+        TC_TRY(build_items(g, 1, light_max, block_pairs, 1, span_max, t.light_bitmap_pairs, &lb_v,
+                           &lb_f, &n_lbitmap, items, s));
     if (split)
-        TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, 1, span_max, &bm_v, &bm_f,
-                           &n_bitmap, items, s));
-    TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, &bl_v,
+        TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, 1, span_max, 0, &bm_v,
+                           &bm_f, &n_bitmap, items, s));
+    TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, 0, &bl_v,
                        &bl_f, &n_block, items, s));
-    TC_TRY(build_items(g, huge_min, 0x7FFFFFFF, block_pairs, 0, 0, &hu_v, &hu_f, &n_huge, items, s));
-    g->n_light = n_wave;
+    TC_TRY(build_items(g, huge_min, 0x7FFFFFFF, block_pairs, 0, 0, 0, &hu_v, &hu_f, &n_huge, items,
+                       s));
+    g->n_light = n_wave + n_lbitmap;
     g->n_heavy = n_block + n_bitmap;
     g->n_huge = n_huge;
     // pairs whose pivot closes nothing are never scanned: their rows stay 0
@@ -886,6 +899,14 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         k_mid_wave<<<(unsigned)blocks, wpb * TC_WAVE, (size_t)wpb * per_wave, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, wv_v, wv_f, n_wave,
             light_max, wave_pairs, g->osup, found);
+        TC_LAUNCHED();
+    }
+    if (n_lbitmap > 0) {
+        const size_t lds = mid_block_bytes(light_max, wpb_block, LK_BITMAP, bw);
+        int64_t blocks = n_lbitmap < 1048576 ? n_lbitmap : 1048576;
+        k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, lb_v, lb_f, n_lbitmap,
+            light_max, block_pairs, bw, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 6, s);

@@ -50,7 +50,7 @@ class tc_tuning(ctypes.Structure):
     _fields_ = [("light_max_dplus", ctypes.c_int32), ("heavy_block", ctypes.c_int32),
                 ("light_block", ctypes.c_int32), ("lds_max_entries", ctypes.c_int32),
                 ("algorithm", ctypes.c_int32), ("item_pairs", ctypes.c_int32),
-                ("bitmap_words", ctypes.c_int32)]
+                ("bitmap_words", ctypes.c_int32), ("light_bitmap_pairs", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -118,6 +118,8 @@ TUNINGS = [None] + [dict(sc, algorithm=a) for a in (1, 2) for sc in _SCHEDULES] 
     {"algorithm": 2, "bitmap_words": 0, "light_max_dplus": 2},
     {"algorithm": 2, "bitmap_words": 256, "light_max_dplus": 2, "item_pairs": 64},
     {"algorithm": 2, "bitmap_words": 8192, "light_max_dplus": 16, "heavy_block": 1024},
+    {"algorithm": 2, "light_bitmap_pairs": 1, "light_max_dplus": 64, "bitmap_words": 256},
+    {"algorithm": 2, "light_bitmap_pairs": 16},
 ]
 
 
