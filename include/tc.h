@@ -105,7 +105,9 @@ const char *tc_status_string(int32_t status);
  *                      lower neighbour u in N_L(v), only the part of N_H(u)
  *                      above v is streamed (Procedure 1's inner loop);
  *                    TC_ALGO_AUTO (0) picks the middle pivot, whose
- *                    streamed work is the number of oriented wedges.
+ *                    streamed work is the number of oriented wedges, for
+ *                    graphs of 600000 edges or more, and the low pivot
+ *                    below (fewer launches and host round trips).
  *                    In the middle-pivot form "rows" are the pivots v and
  *                    the bins above are taken on |N_H(v)| of the pivot.
  *   item_pairs       middle pivot only: lower neighbours of one pivot per

@@ -31,6 +31,7 @@ namespace {
 
 constexpr int BK = 256;
 constexpr int UNROLL = 4;  // independent candidate loads in flight per lane
+constexpr int64_t AUTO_LOW_PIVOT_MAX_EDGES = 600000;
 using namespace tc_tab;
 
 static inline unsigned grid_for(int64_t n, int block = BK) {
@@ -307,7 +308,12 @@ tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
     TC_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     int max_entries = t.lds_max_entries;
     while (max_entries > 1024 && heavy_bytes(max_entries / 2) > (size_t)lds_limit) max_entries >>= 1;
-    const int algo = t.algorithm == TC_ALGO_LOW_PIVOT ? TC_ALGO_LOW_PIVOT : TC_ALGO_MID_PIVOT;
+    // AUTO: the middle pivot streams fewer candidates (the oriented wedges),
+    // but its transposition, work items and fold cost a fixed number of
+    // launches and host round trips; below AUTO_LOW_PIVOT_MAX_EDGES edges
+    // the low pivot finishes first on this device.
+    int algo = t.algorithm;
+    if (algo == TC_ALGO_AUTO) algo = m < AUTO_LOW_PIVOT_MAX_EDGES ? TC_ALGO_LOW_PIVOT : TC_ALGO_MID_PIVOT;
     g->algo_used = algo;
     if (algo == TC_ALGO_MID_PIVOT) return tc_count_mid(g, t, lds_limit, max_entries, found, s);
     const int light_max = t.light_max_dplus;
