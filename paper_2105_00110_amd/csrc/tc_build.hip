@@ -412,20 +412,16 @@ __global__ void k_compact_flags(int32_t n, const uint32_t *__restrict__ f,
 
 static tc_status orient_sorted(tc_graph *g, hipStream_t s);
 
-// Lists the vertices whose flag is set (flags in f, n entries).
-static tc_status compact_vertices(int32_t n, uint32_t *f, int32_t *out, int64_t *count,
+// Lists the vertices whose flag is set (flags in f, n entries); the count
+// goes to the device word *count (read back by the caller with others).
+static tc_status compact_vertices(int32_t n, uint32_t *f, int32_t *out, uint32_t *count,
                                   hipStream_t s) {
     tc_scratch tmp(s);
-    uint32_t *pos = nullptr, *tot = nullptr;
+    uint32_t *pos = nullptr;
     TC_TRY(tmp.get(&pos, n));
-    TC_TRY(tmp.get(&tot, 1));
-    TC_TRY(tc_scan_u32(f, pos, n, tot, s));
+    TC_TRY(tc_scan_u32(f, pos, n, count, s));
     k_compact_flags<<<grid_for(n), BK, 0, s>>>(n, f, pos, out);
     TC_LAUNCHED();
-    uint32_t h = 0;
-    TC_HIP(hipMemcpyAsync(&h, tot, 4, hipMemcpyDeviceToHost, s));
-    TC_HIP(hipStreamSynchronize(s));
-    *count = h;
     return TC_OK;
 }
 
@@ -447,24 +443,38 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     }
     tc_scratch tmp(s);
     int64_t *dplus = nullptr;
-    uint32_t *d_max = nullptr, *flags = nullptr, *cursor = nullptr;
+    uint32_t *info = nullptr, *flags = nullptr, *flags2 = nullptr, *cursor = nullptr;
     uint64_t *tbuf = nullptr;
-    int32_t *list = nullptr;
+    int32_t *list_mid = nullptr, *list_big = nullptr;
     TC_TRY(tmp.get(&cursor, nn));
     TC_TRY(tmp.get(&tbuf, 2 * m));
     TC_TRY(tmp.get(&dplus, nn));
-    TC_TRY(tmp.get(&d_max, 1));
-    TC_HIP(hipMemsetAsync(d_max, 0, 4, s));
+    TC_TRY(tmp.get(&info, 4));  // max d+, mid-list count, big-list count
+    TC_TRY(tmp.get(&flags, nn));
+    TC_TRY(tmp.get(&flags2, nn));
+    TC_TRY(tmp.get(&list_mid, nn));
+    TC_TRY(tmp.get(&list_big, nn));
+    TC_HIP(hipMemsetAsync(info, 0, 16, s));
     TC_HIP(hipMemsetAsync(cursor, 0, sizeof(uint32_t) * nn, s));
     // pass A: buckets of the lower-ordered endpoints
     k_orient_place<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->rank, g->row_ptr, cursor, tbuf);
     TC_LAUNCHED();
     k_dplus_by_rank<<<grid_for(n) < 4096 ? grid_for(n) : 4096, BK, 0, s>>>(n, cursor, g->rank, dplus,
-                                                                          d_max);
+                                                                          info);
     TC_LAUNCHED();
-    uint32_t h_max = 0;
-    TC_HIP(hipMemcpyAsync(&h_max, d_max, 4, hipMemcpyDeviceToHost, s));
+    // the buckets sorted by a wavefront and by a workgroup, listed now so that
+    // one read-back brings their counts with the largest d+
+    k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_WAVE, SEG_MID, flags);
+    TC_LAUNCHED();
+    TC_TRY(compact_vertices(n, flags, list_mid, info + 1, s));
+    k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_MID, 0xFFFFFFFFu, flags2);
+    TC_LAUNCHED();
+    TC_TRY(compact_vertices(n, flags2, list_big, info + 2, s));
+    uint32_t h_info[4] = {0, 0, 0, 0};
+    TC_HIP(hipMemcpyAsync(h_info, info, 16, hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
+    const uint32_t h_max = h_info[0];
+    const int64_t nmid = h_info[1], nblk = h_info[2];
     g->max_dplus = (int32_t)h_max;
     // TC_ORIENT_SEG_MAX (environment) lowers the LDS-sort limit, so that the
     // sort-based path can be exercised on small graphs
@@ -483,28 +493,15 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     k_orient_wave<<<(unsigned)tc_div_up(n, 4), BK, 0, s>>>(n, g->row_ptr, cursor, g->rank, g->orp,
                                                          tbuf, g->ocol, g->o2e, g->orow);
     TC_LAUNCHED();
-    TC_TRY(tmp.get(&flags, nn));
-    TC_TRY(tmp.get(&list, nn));
-    k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_WAVE, SEG_MID, flags);
-    TC_LAUNCHED();
-    int64_t nmid = 0;
-    TC_TRY(compact_vertices(n, flags, list, &nmid, s));
     if (nmid > 0) {
         const int64_t blocks = tc_div_up(nmid, 4);
         k_orient_mid<<<(unsigned)(blocks < 1048576 ? blocks : 1048576), BK, 0, s>>>(
-            list, nmid, g->row_ptr, cursor, g->rank, g->orp, tbuf, g->ocol, g->o2e, g->orow);
+            list_mid, nmid, g->row_ptr, cursor, g->rank, g->orp, tbuf, g->ocol, g->o2e, g->orow);
         TC_LAUNCHED();
     }
-    int32_t *list2 = nullptr;
-    TC_TRY(tmp.get(&list2, nn));
-    k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_MID, 0xFFFFFFFFu, flags);
-    TC_LAUNCHED();
-    int64_t nblk = 0;
-    TC_TRY(compact_vertices(n, flags, list2, &nblk, s));
-    list = list2;
     if (nblk > 0) {
         k_orient_block<<<(unsigned)(nblk < 1048576 ? nblk : 1048576), BK, 0, s>>>(
-            list, nblk, g->row_ptr, cursor, g->rank, g->orp, tbuf, g->ocol, g->o2e, g->orow);
+            list_big, nblk, g->row_ptr, cursor, g->rank, g->orp, tbuf, g->ocol, g->o2e, g->orow);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 3, s);

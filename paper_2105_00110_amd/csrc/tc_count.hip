@@ -235,22 +235,18 @@ __global__ void k_bin_write(int32_t n, const int64_t *__restrict__ orp, int lo, 
     }
 }
 
-// Rows with lo <= d+ <= hi, in rank order; returns their count.
-tc_status select_rows(const tc_graph *g, int lo, int hi, int32_t *out, int64_t *count,
+// Rows with lo <= d+ <= hi, in rank order; their count goes to the device
+// word *count (the caller reads the counts of all bins back at once).
+tc_status select_rows(const tc_graph *g, int lo, int hi, int32_t *out, uint32_t *count,
                       hipStream_t s) {
     tc_scratch tmp(s);
-    uint32_t *pos = nullptr, *tot = nullptr;
+    uint32_t *pos = nullptr;
     TC_TRY(tmp.get(&pos, g->n));
-    TC_TRY(tmp.get(&tot, 1));
     k_bin_flags<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, lo, hi, pos);
     TC_LAUNCHED();
-    TC_TRY(tc_scan_u32(pos, pos, g->n, tot, s));
+    TC_TRY(tc_scan_u32(pos, pos, g->n, count, s));
     k_bin_write<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, lo, hi, pos, out);
     TC_LAUNCHED();
-    uint32_t h = 0;
-    TC_HIP(hipMemcpyAsync(&h, tot, 4, hipMemcpyDeviceToHost, s));
-    TC_HIP(hipStreamSynchronize(s));
-    *count = h;
     return TC_OK;
 }
 
@@ -322,14 +318,19 @@ tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
     int huge_min = max_entries / 2 + 1;
     if (huge_min <= light_max) huge_min = light_max + 1;
     tc_scratch tmp(s);
-    int32_t *rows = nullptr;
+    int32_t *rows = nullptr, *heavy = nullptr, *huge = nullptr;
+    uint32_t *cnt = nullptr;
     TC_TRY(tmp.get(&rows, g->n));
-    int64_t nl = 0, nh = 0, nz = 0;
-    TC_TRY(select_rows(g, 2, light_max, rows, &nl, s));
-    int32_t *heavy = rows + nl;
-    TC_TRY(select_rows(g, light_max + 1, huge_min - 1, heavy, &nh, s));
-    int32_t *huge = heavy + nh;
-    TC_TRY(select_rows(g, huge_min, 0x7FFFFFFF, huge, &nz, s));
+    TC_TRY(tmp.get(&heavy, g->n));
+    TC_TRY(tmp.get(&huge, g->n));
+    TC_TRY(tmp.get(&cnt, 4));
+    TC_TRY(select_rows(g, 2, light_max, rows, cnt, s));
+    TC_TRY(select_rows(g, light_max + 1, huge_min - 1, heavy, cnt + 1, s));
+    TC_TRY(select_rows(g, huge_min, 0x7FFFFFFF, huge, cnt + 2, s));
+    uint32_t hc[4] = {0, 0, 0, 0};
+    TC_HIP(hipMemcpyAsync(hc, cnt, 12, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    const int64_t nl = hc[0], nh = hc[1], nz = hc[2];
     g->n_light = nl;
     g->n_heavy = nh;
     g->n_huge = nz;

@@ -679,23 +679,27 @@ __global__ void k_dplus_write(int32_t n, const int64_t *__restrict__ orp, int lo
     }
 }
 
-tc_status rows_by_dplus(const tc_graph *g, int lo, int hi, int32_t **out, int64_t *count,
-                        tc_scratch &keep, hipStream_t s) {
+// Rows with lo <= |N_H| <= hi for the fold, in the same two phases.
+struct RowPlan {
+    int lo = 2, hi = 0;
+    uint32_t *pos = nullptr;
+    int64_t count = 0;
+    int32_t *rows = nullptr;
+};
+
+tc_status rows_count(const tc_graph *g, RowPlan &p, uint32_t *tot, tc_scratch &keep,
+                     hipStream_t s) {
     const int32_t n = g->n;
-    tc_scratch tmp(s);
-    uint32_t *pos = nullptr, *tot = nullptr;
-    TC_TRY(tmp.get(&pos, n));
-    TC_TRY(tmp.get(&tot, 1));
-    k_dplus_flags<<<grid_for(n), BK, 0, s>>>(n, g->orp, lo, hi, pos);
+    TC_TRY(keep.get(&p.pos, n));
+    k_dplus_flags<<<grid_for(n), BK, 0, s>>>(n, g->orp, p.lo, p.hi, p.pos);
     TC_LAUNCHED();
-    TC_TRY(tc_scan_u32(pos, pos, n, tot, s));
-    uint32_t h = 0;
-    TC_HIP(hipMemcpyAsync(&h, tot, 4, hipMemcpyDeviceToHost, s));
-    TC_HIP(hipStreamSynchronize(s));
-    *count = h;
-    TC_TRY(keep.get(out, h));
-    if (h > 0) {
-        k_dplus_write<<<grid_for(n), BK, 0, s>>>(n, g->orp, lo, hi, pos, *out);
+    return tc_scan_u32(p.pos, p.pos, n, tot, s);
+}
+
+tc_status rows_write(const tc_graph *g, RowPlan &p, tc_scratch &keep, hipStream_t s) {
+    TC_TRY(keep.get(&p.rows, p.count));
+    if (p.count > 0) {
+        k_dplus_write<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, p.lo, p.hi, p.pos, p.rows);
         TC_LAUNCHED();
     }
     return TC_OK;
@@ -755,27 +759,35 @@ __global__ void k_mid_pivots(int32_t n, const int64_t *__restrict__ orp,
     }
 }
 
-tc_status build_items(const tc_graph *g, int lo, int hi, int S, int sel, int64_t span_max,
-                      int64_t pairs_min, int32_t **item_v, uint32_t **item_first, int64_t *count,
-                      tc_scratch &keep, hipStream_t s) {
+// Work-item lists are built in two phases so that one read-back serves all
+// of them: count (per-pivot item counts and their scan; the total stays on
+// the device), then, with the totals on the host, allocate and write.
+struct ItemPlan {
+    int lo = 1, hi = 0, S = 64, sel = 0;
+    int64_t span_max = 0, pairs_min = 0;
+    uint32_t *cnt = nullptr, *off = nullptr;
+    int64_t count = 0;
+    int32_t *item_v = nullptr;
+    uint32_t *item_first = nullptr;
+};
+
+tc_status plan_count(const tc_graph *g, ItemPlan &p, uint32_t *tot, tc_scratch &keep,
+                     hipStream_t s) {
     const int32_t n = g->n;
-    tc_scratch tmp(s);
-    uint32_t *cnt = nullptr, *off = nullptr, *tot = nullptr;
-    TC_TRY(tmp.get(&cnt, n));
-    TC_TRY(tmp.get(&off, n));
-    TC_TRY(tmp.get(&tot, 1));
-    k_item_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, lo, hi, S, sel,
-                                            span_max, pairs_min, cnt);
+    TC_TRY(keep.get(&p.cnt, n));
+    TC_TRY(keep.get(&p.off, n));
+    k_item_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, p.lo, p.hi, p.S, p.sel,
+                                            p.span_max, p.pairs_min, p.cnt);
     TC_LAUNCHED();
-    TC_TRY(tc_scan_u32(cnt, off, n, tot, s));
-    uint32_t h = 0;
-    TC_HIP(hipMemcpyAsync(&h, tot, 4, hipMemcpyDeviceToHost, s));
-    TC_HIP(hipStreamSynchronize(s));
-    *count = h;
-    TC_TRY(keep.get(item_v, h));
-    TC_TRY(keep.get(item_first, h));
-    if (h > 0) {
-        k_item_write<<<grid_for(n), BK, 0, s>>>(n, cnt, off, g->in_ptr, S, *item_v, *item_first);
+    return tc_scan_u32(p.cnt, p.off, n, tot, s);
+}
+
+tc_status plan_write(const tc_graph *g, ItemPlan &p, tc_scratch &keep, hipStream_t s) {
+    TC_TRY(keep.get(&p.item_v, p.count));
+    TC_TRY(keep.get(&p.item_first, p.count));
+    if (p.count > 0) {
+        k_item_write<<<grid_for(g->n), BK, 0, s>>>(g->n, p.cnt, p.off, g->in_ptr, p.S, p.item_v,
+                                                  p.item_first);
         TC_LAUNCHED();
     }
     return TC_OK;
@@ -853,9 +865,6 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     const int wave_pairs = t.item_pairs;
     const int block_pairs = t.item_pairs * wpb_block;
     tc_scratch items(s);
-    int32_t *wv_v = nullptr, *bl_v = nullptr, *bm_v = nullptr, *hu_v = nullptr;
-    uint32_t *wv_f = nullptr, *bl_f = nullptr, *bm_f = nullptr, *hu_f = nullptr;
-    int64_t n_wave = 0, n_block = 0, n_bitmap = 0, n_huge = 0;
     // workgroup pivots whose rank span fits the LDS bitmap use it; the
     // others hash (or, above huge_min, search device memory).  Wavefront
     // pivots with at least light_bitmap_pairs pairs and a span that fits go
@@ -864,21 +873,43 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     const int64_t span_max = 32 * (int64_t)bw;
     const int split = bw > 0 ? 1 : 0;
     const int lsplit = (bw > 0 && t.light_bitmap_pairs > 0) ? 1 : 0;
-    int32_t *lb_v = nullptr;
-    uint32_t *lb_f = nullptr;
-    int64_t n_lbitmap = 0;
-    TC_TRY(build_items(g, 1, light_max, wave_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs,
-                       &wv_v, &wv_f, &n_wave, items, s));
-    if (lsplit)
-        TC_TRY(build_items(g, 1, light_max, block_pairs, 1, span_max, t.light_bitmap_pairs, &lb_v,
-                           &lb_f, &n_lbitmap, items, s));
-    if (split)
-        TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, 1, span_max, 0, &bm_v,
-                           &bm_f, &n_bitmap, items, s));
-    TC_TRY(build_items(g, light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, 0, &bl_v,
-                       &bl_f, &n_block, items, s));
-    TC_TRY(build_items(g, huge_min, 0x7FFFFFFF, block_pairs, 0, 0, 0, &hu_v, &hu_f, &n_huge, items,
-                       s));
+    enum { P_WAVE, P_LBITMAP, P_BITMAP, P_BLOCK, P_HUGE, NPLANS };
+    ItemPlan pl[NPLANS];
+    pl[P_WAVE] = {1, light_max, wave_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs};
+    pl[P_LBITMAP] = {1, lsplit ? light_max : 0, block_pairs, 1, span_max, t.light_bitmap_pairs};
+    pl[P_BITMAP] = {light_max + 1, split ? huge_min - 1 : light_max, block_pairs, 1, span_max, 0};
+    pl[P_BLOCK] = {light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, 0};
+    pl[P_HUGE] = {huge_min, 0x7FFFFFFF, block_pairs, 0, 0, 0};
+    RowPlan rp[2];
+    rp[0].lo = 2;
+    rp[0].hi = 64;
+    rp[1].lo = 65;
+    rp[1].hi = 0x7FFFFFFF;
+    uint32_t *tots = nullptr;
+    TC_TRY(items.get(&tots, NPLANS + 2));
+    for (int i = 0; i < NPLANS; ++i) TC_TRY(plan_count(g, pl[i], tots + i, items, s));
+    if (g->bit_words > 0)
+        for (int i = 0; i < 2; ++i) TC_TRY(rows_count(g, rp[i], tots + NPLANS + i, items, s));
+    uint32_t h_tots[NPLANS + 2] = {};
+    TC_HIP(hipMemcpyAsync(h_tots, tots, sizeof(h_tots), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < NPLANS; ++i) {
+        pl[i].count = h_tots[i];
+        TC_TRY(plan_write(g, pl[i], items, s));
+    }
+    if (g->bit_words > 0)
+        for (int i = 0; i < 2; ++i) {
+            rp[i].count = h_tots[NPLANS + i];
+            TC_TRY(rows_write(g, rp[i], items, s));
+        }
+    const int64_t n_wave = pl[P_WAVE].count, n_lbitmap = pl[P_LBITMAP].count;
+    const int64_t n_bitmap = pl[P_BITMAP].count, n_block = pl[P_BLOCK].count;
+    const int64_t n_huge = pl[P_HUGE].count;
+    int32_t *wv_v = pl[P_WAVE].item_v, *lb_v = pl[P_LBITMAP].item_v, *bm_v = pl[P_BITMAP].item_v;
+    int32_t *bl_v = pl[P_BLOCK].item_v, *hu_v = pl[P_HUGE].item_v;
+    uint32_t *wv_f = pl[P_WAVE].item_first, *lb_f = pl[P_LBITMAP].item_first;
+    uint32_t *bm_f = pl[P_BITMAP].item_first, *bl_f = pl[P_BLOCK].item_first;
+    uint32_t *hu_f = pl[P_HUGE].item_first;
     g->n_light = n_wave + n_lbitmap;
     g->n_heavy = n_block + n_bitmap;
     g->n_huge = n_huge;
@@ -939,10 +970,8 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     }
     tc_prof_mark(g, 8, s);
     if (g->bit_words > 0) {
-        int32_t *small = nullptr, *big = nullptr;
-        int64_t ns = 0, nb = 0;
-        TC_TRY(rows_by_dplus(g, 2, 64, &small, &ns, items, s));
-        TC_TRY(rows_by_dplus(g, 65, 0x7FFFFFFF, &big, &nb, items, s));
+        int32_t *small = rp[0].rows, *big = rp[1].rows;
+        const int64_t ns = rp[0].count, nb = rp[1].count;
         if (ns > 0) {
             int64_t fb = tc_div_up(ns, BK / 16);
             k_fold<16><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK, 0, s>>>(

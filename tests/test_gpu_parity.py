@@ -347,3 +347,16 @@ def test_big_clique_fold_two_stripe_groups(tclib):
     assert np.all(r["tri"] == (k - 1) * (k - 2) // 2)
     assert int(r["triG"][0]) == k * (k - 1) * (k - 2) // 6
     assert np.all(r["tc"] == 1.0)
+
+
+def test_auto_pivot_choice(tclib):
+    # TC_ALGO_AUTO: the low pivot for small graphs, the middle pivot from
+    # 600000 edges up; the work statistics report the form that ran
+    cases = [(gg.er(2000, 0.005, seed=1), tclib.TC_ALGO_LOW_PIVOT),
+             (gg.rmat(17, 16, seed=17), tclib.TC_ALGO_MID_PIVOT)]
+    for (src, dst, n), want in cases:
+        g = tclib.Graph.from_edges(torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n)
+        g.compute()
+        _say("auto pivot, m", g.m)
+        assert g.work_stats()["algorithm"] == want
+        g.close()
