@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "tc_internal.h"
@@ -17,9 +18,10 @@ tc_status tc_map_hip_error(hipError_t e) {
     return TC_ERR_DEVICE;
 }
 
-static bool g_profiling = false;
+// read by compute calls that may run on several host threads at once
+static std::atomic<bool> g_profiling{false};
 
-bool tc_profiling_on() { return g_profiling; }
+bool tc_profiling_on() { return g_profiling.load(std::memory_order_relaxed); }
 
 void tc_prof_mark(tc_graph *g, int idx, hipStream_t s) {
     if (!g->prof || idx < 0 || idx >= TC_PROF_MARKS) return;
@@ -160,7 +162,7 @@ tc_status new_graph(int32_t n, int32_t num_graphs, tc_graph **out) {
     TC_HIP(hipGetDevice(&g->device));
     g->n = n;
     g->num_graphs = num_graphs;
-    g->prof = g_profiling;
+    g->prof = tc_profiling_on();
     int b = tc_bits_for(n > 1 ? (uint64_t)(n - 1) : 1);
     g->bits = b < 1 ? 1 : b;
     *out = g;
@@ -384,7 +386,7 @@ tc_status tc_compute_tuned(tc_graph *g, const tc_tuning *tuning, void *stream) {
     g->last_stream = s;
     g->computed = false;
     g->prof_compute = false;
-    g->prof = g_profiling;  // the switch as it stands when this compute starts
+    g->prof = tc_profiling_on();  // the switch as it stands when this compute starts
     tc_prof_mark(g, 4, s);
     TC_TRY(tc_count(g, tuning, s));
     TC_TRY(tc_aggregate(g, s));
