@@ -322,6 +322,15 @@ enum {
 };
 
 tc_status tc_set_profiling(int32_t on);
+
+/* Device memory.  The library keeps the device memory of destroyed handles
+ * and of its temporaries cached for reuse (per device; a block freed on one
+ * stream is reused on another only after that stream's work on it is
+ * done), so a sequence of builds allocates only when it needs more than
+ * before.  tc_trim_memory returns every cached block that no live handle
+ * uses to the device (it waits for their last work); live handles are
+ * untouched.  Thread-safe. */
+tc_status tc_trim_memory(void);
 tc_status tc_get_stage_ms(const tc_graph *g, double *ms);
 tc_status tc_get_work_stats(tc_graph *g, int64_t *stats, void *stream);
 

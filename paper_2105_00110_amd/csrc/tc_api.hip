@@ -4,7 +4,9 @@
 #include <string.h>
 
 #include <atomic>
+#include <map>
 #include <mutex>
+#include <unordered_map>
 
 #include "tc_internal.h"
 
@@ -34,36 +36,103 @@ void tc_prof_mark(tc_graph *g, int idx, hipStream_t s) {
     if (idx == 11) g->prof_compute = true;
 }
 
-static std::mutex g_pool_mu;
-static bool g_pool_ready[64];
+// ---------------------------------------------------------------------------
+// Device memory: a caching allocator of the library's own.
+//
+// Blocks come from hipMalloc and, once freed, stay cached per device in a
+// best-fit free list (sizes rounded to 512 B below 1 MiB and to 2 MiB
+// above; a block is reused for requests of at least half its size).  A free
+// records an event on the freeing stream; a reuse on the same stream needs
+// nothing (stream order), a reuse on another stream waits for that event.
+// So repeated builds of similar graphs allocate nothing new, without the
+// trimming and regrowth of the runtime's stream-ordered pool, whose regrowth
+// stalled builds by seconds.  tc_trim_memory() returns cached blocks.
+// ---------------------------------------------------------------------------
+namespace {
 
-static void pool_setup(int dev) {
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    if (dev < 0 || dev >= 64 || g_pool_ready[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = ~0ull;  // keep freed blocks cached in the pool
-        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    g_pool_ready[dev] = true;
+struct Block {
+    size_t size = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    int device = 0;
+};
+
+constexpr int MAX_DEV = 64;
+std::mutex g_alloc_mu;
+std::multimap<size_t, std::pair<void *, Block>> g_free[MAX_DEV];
+std::unordered_map<void *, Block> g_used;
+
+size_t round_size(size_t b) {
+    if (b < ((size_t)1 << 20)) return (b + 511) & ~(size_t)511;
+    const size_t g = (size_t)2 << 20;
+    return (b + g - 1) / g * g;
 }
+
+// Frees the cached blocks of one device (caller holds the lock).
+void release_cached(int dev) {
+    for (auto &kv : g_free[dev]) {
+        Block &b = kv.second.second;
+        if (b.ev) {
+            (void)hipEventSynchronize(b.ev);
+            (void)hipEventDestroy(b.ev);
+        }
+        (void)hipFree(kv.second.first);
+    }
+    g_free[dev].clear();
+}
+
+}  // namespace
 
 tc_status tc_dev_alloc(void **p, size_t bytes, hipStream_t s) {
     int dev = 0;
     TC_HIP(hipGetDevice(&dev));
-    pool_setup(dev);
+    if (dev < 0 || dev >= MAX_DEV) return TC_ERR_DEVICE;
     *p = nullptr;
-    hipError_t e = hipMallocAsync(p, bytes, s);
+    const size_t size = round_size(bytes > 0 ? bytes : 1);
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto &fl = g_free[dev];
+    auto it = fl.lower_bound(size);
+    if (it != fl.end() && it->first <= 2 * size) {
+        void *ptr = it->second.first;
+        Block b = it->second.second;
+        fl.erase(it);
+        if (b.stream != s && b.ev) TC_HIP(hipStreamWaitEvent(s, b.ev, 0));
+        b.stream = s;
+        g_used[ptr] = b;
+        *p = ptr;
+        return TC_OK;
+    }
+    void *ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, size);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        *p = nullptr;
-        return tc_map_hip_error(e);
+        release_cached(dev);  // give the cache back and try once more
+        e = hipMalloc(&ptr, size);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return tc_map_hip_error(e);
+        }
     }
+    Block b;
+    b.size = size;
+    b.stream = s;
+    b.device = dev;
+    g_used[ptr] = b;
+    *p = ptr;
     return TC_OK;
 }
 
 void tc_dev_free(void *p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_used.find(p);
+    if (it == g_used.end()) return;
+    Block b = it->second;
+    g_used.erase(it);
+    if (!b.ev && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) b.ev = nullptr;
+    if (b.ev) (void)hipEventRecord(b.ev, s);
+    b.stream = s;
+    g_free[b.device].emplace(b.size, std::make_pair(p, b));
 }
 
 // ---------------------------------------------------------------------------
@@ -513,6 +582,19 @@ tc_status tc_top_k(const tc_graph *g, int32_t k, int32_t *vertices, double *valu
         if (values) TC_TRY(copy_out(values, dval, sizeof(double) * k, mem_kind, s));
         TC_HIP(hipStreamSynchronize(s));
     }
+    return TC_OK;
+}
+
+tc_status tc_trim_memory(void) {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    int cur = 0;
+    TC_HIP(hipGetDevice(&cur));
+    for (int d = 0; d < MAX_DEV; ++d) {
+        if (g_free[d].empty()) continue;
+        if (d != cur) TC_HIP(hipSetDevice(d));
+        release_cached(d);
+    }
+    TC_HIP(hipSetDevice(cur));
     return TC_OK;
 }
 

@@ -77,6 +77,7 @@ _SIGS = {
     "tc_get_edges": (_st, [_vp, _vp, _vp, _i32, _vp]),
     "tc_get_results": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "tc_numerator_algebraic": (_st, [_vp, _vp, _i32, _vp]),
+    "tc_trim_memory": (_st, []),
     "tc_edge_text_read": (_st, [ctypes.c_char_p, _vp, _vp, _i64, ctypes.POINTER(_i64),
                                 ctypes.POINTER(_i64), _i32]),
     "tc_relabel_ids": (_st, [_vp, _vp, _i64, _vp, _vp, _vp, ctypes.POINTER(_i64), _i32, _vp]),
@@ -261,6 +262,10 @@ def tc_top_k(h, k, vertices, values, mem_kind, stream):
     _check(load().tc_top_k(h, int(k), vertices, values, ctypes.byref(ko), int(mem_kind), stream),
            "tc_top_k")
     return int(ko.value)
+
+
+def tc_trim_memory():
+    return _check(load().tc_trim_memory(), "tc_trim_memory")
 
 
 def tc_set_profiling(on):

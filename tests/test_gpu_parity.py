@@ -360,3 +360,24 @@ def test_auto_pivot_choice(tclib):
         _say("auto pivot, m", g.m)
         assert g.work_stats()["algorithm"] == want
         g.close()
+
+
+def test_cached_memory_across_streams_and_trim(tclib):
+    # blocks freed on one stream are reused on another only after that
+    # stream's work on them is done; trimming returns them; results stay exact
+    src, dst, n = gg.rmat(15, 16, seed=15)
+    ref = native.o1_definition(src, dst, n)
+    ds, dd = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(4):
+        st = streams[rep % 2]
+        with torch.cuda.stream(st):
+            g = tclib.Graph.from_edges(ds, dd, n, stream=st.cuda_stream)
+            g.compute({"algorithm": 2})
+            r = g.results()
+            r["eu"], r["ev"] = g.edges()
+            r["status"], r["m"] = g.status, g.m
+            g.close()
+        assert_parity(r, ref)
+        if rep == 2:
+            tclib.tc_trim_memory()
