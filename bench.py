@@ -327,7 +327,48 @@ def served_leg(args, autotune):
         log(f"served at {frac}x capacity: {json.dumps(run)}")
         out["runs"].append(run)
         del replies
+    out["resident"] = resident_run(reqs, cfg, capacity)
     return out
+
+
+def resident_run(reqs, cfg, capacity):
+    """Resident graphs: the first 200 requests are kept on the device under
+    their keys; 800 further requests ask for the top-10 vertices or the
+    values of 100 vertices of one of them, at 0.8x the closed-loop rate."""
+    import dataclasses
+
+    import numpy as np
+    from paper_2105_00110_amd import graphgen as gg
+    from paper_2105_00110_amd import serve
+
+    K, Q = 200, 800
+    base = reqs[:K]
+    pick = (gg.uniform(Q, 5, 0x71) * K).astype(np.int64)
+    kind = gg.uniform(Q, 5, 0x72)
+    mix = [dataclasses.replace(r, rid=i, key=("g", i)) for i, r in enumerate(base)]
+    for j in range(Q):
+        i = int(pick[j])
+        if kind[j] < 0.5:
+            q = ("topk", 10)
+        else:
+            ids = (gg.uniform(100, 7 + j, 0x73) * base[i].n).astype(np.int64)
+            q = ("vertices", ids)
+        mix.append(dataclasses.replace(base[i], rid=len(mix), key=("g", i), query=q))
+    rate = 0.8 * capacity
+    srv = serve.Server(cfg)
+    replies = srv.run(mix, serve.poisson_arrivals(len(mix), rate, seed=6))
+    hits = [r for r in replies[K:] if r.error is None]
+    builds = [r for r in replies[:K] if r.error is None]
+    res = {"graphs": K, "queries": Q, "rate_per_s": round(rate, 2),
+           "builds": {k: round(v, 3) for k, v in serve.latency_summary(builds).items()},
+           "queries_on_resident": {k: round(v, 3) for k, v in serve.latency_summary(hits, 0.0).items()},
+           "graphs_per_s": len(replies) / srv.makespan,
+           "errors": len(replies) - len(hits) - len(builds),
+           "resident_hits": srv.stats["resident_hits"], "evictions": srv.stats["evictions"],
+           "resident_bytes_at_end": srv.resident_bytes}
+    srv.close()
+    log(f"served, resident graphs: {json.dumps(res)}")
+    return res
 
 
 def main():

@@ -21,11 +21,17 @@ How the loop works:
   Units that arrive while others run overlap with them on the device.
 * Resident state.  The CSR, the orientation and the counts of a unit stay
   in device memory from the build to the copy of its results.  Nothing
-  goes through the host in between.
+  goes through the host in between.  A request with a cache key keeps its
+  graph resident after it is answered (its device bytes count against the
+  budget); later requests with the same key -- for the full results, the
+  top-k vertices or the values of given vertices -- are answered from the
+  resident handle without a new build or count.  Resident graphs are
+  evicted least recently used when a new unit needs their memory.
 
 The integer arithmetic is the same whether a request runs alone, in a batch
 or next to other units: every result is bit-identical (tests check it).
 """
+import collections
 import concurrent.futures as cf
 import hashlib
 import math
@@ -51,6 +57,8 @@ class Request:
     family: str = ""
     seed: int = 0
     arrival: float = 0.0  # seconds after the start of the run
+    key: object = None    # cache key: keep the graph resident for later queries
+    query: tuple = ("full",)  # ("full",) | ("topk", k) | ("vertices", ids)
 
     @property
     def pairs(self):
@@ -151,14 +159,36 @@ def _split(results, reqs, vtx_off, edge_off):
     return out
 
 
-def run_alone(req, stream, tuning=None):
-    """One request through its own handle: build, compute, copy out."""
+def answer(g, query):
+    """The reply to one query on a computed handle."""
+    kind = query[0]
+    if kind == "full":
+        return g.results()
+    if kind == "topk":
+        verts, vals = g.top_k(int(query[1]))
+        return {"vertices": verts, "tc": vals}
+    if kind == "vertices":
+        import torch
+        ids = torch.as_tensor(np.ascontiguousarray(query[1], np.int64), device="cuda")
+        r = g.results_device()
+        return {k: r[k].index_select(0, ids).cpu().numpy() for k in ("tri", "num", "tc")}
+    raise ValueError(f"unknown query {kind!r}")
+
+
+def run_alone(req, stream, tuning=None, keep=False):
+    """One request through its own handle: build, compute, answer.  With
+    keep, returns (reply, handle) and leaves the handle open."""
     g = tc.Graph.from_edges(req.src, req.dst, req.n, stream=stream)
     try:
         g.compute(tuning)
-        return g.results()
-    finally:
+        out = answer(g, req.query)
+    except BaseException:
         g.close()
+        raise
+    if keep:
+        return out, g
+    g.close()
+    return out
 
 
 def run_unit(reqs, stream, tuning=None):
@@ -202,6 +232,7 @@ class _Unit:
     reqs: list
     bytes: int
     stream_idx: int = -1
+    hit: object = None  # resident entry answering the request, if any
 
 
 class Server:
@@ -210,21 +241,50 @@ class Server:
         self.cfg = cfg or ServerConfig()
         self.streams = [torch.cuda.Stream() for _ in range(self.cfg.streams)]
         self.stats = {"units": 0, "batched_units": 0, "batched_requests": 0, "rejected": 0,
-                      "peak_bytes": 0, "max_concurrent_units": 0}
+                      "peak_bytes": 0, "max_concurrent_units": 0, "resident_hits": 0,
+                      "evictions": 0}
+        # key -> {"g": handle, "bytes": device bytes, "busy": bool}, oldest first
+        self.resident = collections.OrderedDict()
+        self.resident_bytes = 0
+
+    def _evict_for(self, need, free_bytes):
+        """Closes least recently used idle resident graphs until need bytes
+        fit; returns the new free byte count."""
+        for key in list(self.resident):
+            if free_bytes >= need:
+                break
+            e = self.resident[key]
+            if e["busy"]:
+                continue
+            e["g"].close()
+            del self.resident[key]
+            self.resident_bytes -= e["bytes"]
+            free_bytes += e["bytes"]
+            self.stats["evictions"] += 1
+        return free_bytes
 
     def _form_unit(self, q, free_bytes):
         """Next unit from the head of the queue, or None if it must wait."""
         head = q[0]
+        if head.key is not None and head.key in self.resident:
+            e = self.resident[head.key]
+            if e["busy"]:
+                return None
+            self.resident.move_to_end(head.key)
+            return _Unit([head], 0, hit=e)
         est = estimate_bytes([head])
         if est > self.cfg.budget_bytes:
             return _REJECT
         if est > free_bytes:
-            return None
-        if head.pairs >= self.cfg.small_pairs:
+            free_bytes = self._evict_for(est, free_bytes)
+            if est > free_bytes:
+                return None
+        if head.pairs >= self.cfg.small_pairs or head.key is not None or head.query[0] != "full":
             return _Unit([head], est)
         reqs, pairs = [], 0
         for r in q:
-            if r.pairs >= self.cfg.small_pairs or pairs + r.pairs > self.cfg.batch_pairs:
+            if (r.pairs >= self.cfg.small_pairs or pairs + r.pairs > self.cfg.batch_pairs
+                    or r.key is not None or r.query[0] != "full"):
                 break
             e = estimate_bytes(reqs + [r])
             if e > free_bytes:
@@ -250,12 +310,23 @@ class Server:
         completed = 0
 
         def work(unit):
+            kept = None
             try:
-                res = run_unit(unit.reqs, self.streams[unit.stream_idx].cuda_stream, self.cfg.tuning)
+                st = self.streams[unit.stream_idx].cuda_stream
+                r0 = unit.reqs[0]
+                if unit.hit is not None:
+                    g = unit.hit["g"]
+                    g.stream = st
+                    res = [answer(g, r0.query)]
+                elif r0.key is not None:
+                    out, kept = run_alone(r0, st, self.cfg.tuning, keep=True)
+                    res = [out]
+                else:
+                    res = run_unit(unit.reqs, st, self.cfg.tuning)
                 err = None
             except Exception as e:  # a failed unit answers its requests with the error
                 res, err = None, repr(e)
-            done_q.put((unit, res, err, time.perf_counter() - t0))
+            done_q.put((unit, res, err, time.perf_counter() - t0, kept))
 
         with cf.ThreadPoolExecutor(max_workers=len(self.streams)) as ex:
             while completed < len(requests):
@@ -266,7 +337,7 @@ class Server:
                     q.append(r)
                     nxt += 1
                 while q and free_streams:
-                    unit = self._form_unit(q, self.cfg.budget_bytes - used)
+                    unit = self._form_unit(q, self.cfg.budget_bytes - used - self.resident_bytes)
                     if unit is None:
                         break
                     if unit is _REJECT:
@@ -278,8 +349,11 @@ class Server:
                         continue
                     del q[:len(unit.reqs)]
                     unit.stream_idx = free_streams.pop()
+                    if unit.hit is not None:
+                        unit.hit["busy"] = True
+                        self.stats["resident_hits"] += 1
                     used += unit.bytes
-                    self.stats["peak_bytes"] = max(self.stats["peak_bytes"], used)
+                    self.stats["peak_bytes"] = max(self.stats["peak_bytes"], used + self.resident_bytes)
                     self.stats["units"] += 1
                     if len(unit.reqs) > 1:
                         self.stats["batched_units"] += 1
@@ -295,23 +369,42 @@ class Server:
                 if not in_flight and timeout is None and not q:
                     break
                 try:
-                    unit, res, err, t_done = done_q.get(timeout=timeout)
+                    unit, res, err, t_done, kept = done_q.get(timeout=timeout)
                 except queue.Empty:
                     continue
                 while True:
                     del in_flight[id(unit)]
                     used -= unit.bytes
                     free_streams.append(unit.stream_idx)
+                    if unit.hit is not None:
+                        unit.hit["busy"] = False
+                    if kept is not None:
+                        key = unit.reqs[0].key
+                        if key in self.resident:  # built twice while queued: keep one
+                            kept.close()
+                        else:
+                            b = kept.device_bytes()
+                            self.resident[key] = {"g": kept, "bytes": b, "busy": False}
+                            self.resident_bytes += b
+                            self.stats["peak_bytes"] = max(self.stats["peak_bytes"],
+                                                           used + self.resident_bytes)
                     for i, r in enumerate(unit.reqs):
                         replies[r.rid] = Reply(r.rid, res[i] if res else None, err, r.arrival,
                                                t_done, len(unit.reqs))
                         completed += 1
                     try:
-                        unit, res, err, t_done = done_q.get_nowait()
+                        unit, res, err, t_done, kept = done_q.get_nowait()
                     except queue.Empty:
                         break
         self.makespan = time.perf_counter() - t0
         return replies
+
+    def close(self):
+        """Releases every resident graph."""
+        for e in self.resident.values():
+            e["g"].close()
+        self.resident.clear()
+        self.resident_bytes = 0
 
 
 def closed_loop(requests, stream, tuning=None):

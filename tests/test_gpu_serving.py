@@ -4,7 +4,9 @@
   graphs bit-exact against the oracle, every graph's invariants, and the
   whole batch equal to one graph per launch on a prefix of the graphs.
 * Serving: every reply of a mixed, overlapping, batched run equals the same
-  request run alone (bit for bit), and sampled replies equal the oracle.
+  request run alone (bit for bit), and sampled replies equal the oracle;
+  graphs kept resident answer later top-k and vertex queries, also under a
+  budget tight enough to evict them.
 * Autotuner: a short search leaves every result unchanged.
 """
 import numpy as np
@@ -166,3 +168,45 @@ def test_autotune_keeps_results(tclib, tmp_path):
     p = str(tmp_path / "t.json")
     autotune.store("rmat_s14", out, p)
     assert autotune.load("rmat_s14", p) == out["tuning"]
+
+
+def test_serving_resident_graphs_answer_later_queries(tclib):
+    # keyed requests keep their graphs resident; later top-k and vertex
+    # queries on the same keys are answered from them, equal to the graph
+    # run alone; a tight budget evicts and rebuilds without changing answers
+    import dataclasses
+    from paper_2105_00110_amd import serve
+    base = serve.make_requests(6, seed=31, m_lo=2e3, m_hi=2e5, workers=6)
+    stream = torch.cuda.Stream()
+    alone = [serve.run_alone(r, stream.cuda_stream) for r in base]
+    rng = np.random.default_rng(31)
+    reqs = [dataclasses.replace(r, rid=i, key=("g", i)) for i, r in enumerate(base)]
+    for j in range(24):
+        i = int(rng.integers(0, len(base)))
+        if j % 2:
+            q = ("topk", 5)
+        else:
+            q = ("vertices", rng.integers(0, base[i].n, 7))
+        reqs.append(dataclasses.replace(base[i], rid=len(reqs), key=("g", i), query=q))
+    for budget in (8 << 30, 2 * max(serve.estimate_bytes([r]) for r in base)):
+        srv = serve.Server(serve.ServerConfig(budget_bytes=budget, streams=3))
+        replies = srv.run(reqs, serve.poisson_arrivals(len(reqs), 2000.0, seed=31))
+        _say("resident serving, budget", budget, srv.stats)
+        assert all(r.error is None for r in replies)
+        assert srv.stats["resident_hits"] > 0
+        for rq, rp in zip(reqs, replies):
+            i = rq.key[1]
+            a = alone[i]
+            if rq.query[0] == "full":
+                np.testing.assert_array_equal(rp.results["support"], a["support"])
+                np.testing.assert_array_equal(rp.results["tc"].view(np.uint64), a["tc"].view(np.uint64))
+            elif rq.query[0] == "topk":
+                order = np.lexsort((np.arange(len(a["tc"])), -a["tc"]))[:5]
+                np.testing.assert_array_equal(rp.results["vertices"], order)
+                np.testing.assert_array_equal(rp.results["tc"].view(np.uint64), a["tc"][order].view(np.uint64))
+            else:
+                ids = rq.query[1]
+                np.testing.assert_array_equal(rp.results["tri"].view(np.uint64), a["tri"][ids])
+                np.testing.assert_array_equal(rp.results["num"].view(np.uint64), a["num"][ids])
+                np.testing.assert_array_equal(rp.results["tc"].view(np.uint64), a["tc"][ids].view(np.uint64))
+        srv.close()

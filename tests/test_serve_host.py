@@ -1,4 +1,5 @@
 """Host logic of the serving loop and the autotuner (no GPU)."""
+import collections
 import math
 
 import numpy as np
@@ -43,11 +44,12 @@ def test_make_graph_sizes(fam):
 
 
 class _R:
-    def __init__(self, rid, pairs, n=10):
+    def __init__(self, rid, pairs, n=10, key=None, query=("full",)):
         self.rid, self.n = rid, n
         self.src = np.zeros(pairs, np.int32)
         self.dst = np.zeros(pairs, np.int32)
         self.arrival = 0.0
+        self.key, self.query = key, query
 
     @property
     def pairs(self):
@@ -59,7 +61,48 @@ def _server(monkeypatch, **cfg):
     monkeypatch.setattr(serve, "estimate_bytes", lambda reqs: 100 * sum(r.pairs for r in reqs))
     s = serve.Server.__new__(serve.Server)
     s.cfg = serve.ServerConfig(**cfg)
+    s.stats = {"evictions": 0}
+    s.resident = collections.OrderedDict()
+    s.resident_bytes = 0
     return s
+
+
+class _G:
+    def __init__(self):
+        self.closed = False
+
+    def close(self):
+        self.closed = True
+
+
+def test_form_unit_resident_hit_and_keyed_alone(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250)
+    g = _G()
+    s.resident["a"] = {"g": g, "bytes": 5000, "busy": False}
+    s.resident_bytes = 5000
+    u = s._form_unit([_R(0, 50, key="a", query=("topk", 3)), _R(1, 50)], 10**9)
+    assert u.hit is s.resident["a"] and u.bytes == 0 and [r.rid for r in u.reqs] == [0]
+    s.resident["a"]["busy"] = True
+    assert s._form_unit([_R(0, 50, key="a")], 10**9) is None  # wait for the busy graph
+    # a keyed request that is not resident is built alone, never batched
+    u = s._form_unit([_R(2, 50, key="b"), _R(3, 50)], 10**9)
+    assert [r.rid for r in u.reqs] == [2] and u.hit is None
+    # a batch stops before a keyed request
+    u = s._form_unit([_R(4, 50), _R(5, 50, key="c"), _R(6, 50)], 10**9)
+    assert [r.rid for r in u.reqs] == [4]
+
+
+def test_form_unit_evicts_least_recently_used(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=20000, small_pairs=100, batch_pairs=250)
+    gs = [_G() for _ in range(3)]
+    for i, g in enumerate(gs):
+        s.resident[i] = {"g": g, "bytes": 6000, "busy": i == 0}
+    s.resident_bytes = 18000
+    # 9000 bytes needed, 2000 free: the busy oldest entry is skipped, the next two go
+    u = s._form_unit([_R(0, 90)], 2000)
+    assert u is not None and u.bytes == 9000
+    assert [g.closed for g in gs] == [False, True, True]
+    assert list(s.resident) == [0] and s.resident_bytes == 6000 and s.stats["evictions"] == 2
 
 
 def test_form_unit_batches_small_in_order(monkeypatch):
