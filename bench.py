@@ -324,7 +324,7 @@ def served_leg(args, autotune):
                                                                 else v for k, v in summ.items()},
                "graphs_per_s": len(ok) / srv.makespan, "makespan_s": round(srv.makespan, 3),
                "errors": len(replies) - len(ok), "mix_equals_alone": bool(same), **srv.stats}
-        log(f"served at {frac}x capacity: {json.dumps(run)}")
+        log(f"served at {f'{frac}x capacity' if frac else 'saturation'}: {json.dumps(run)}")
         out["runs"].append(run)
         del replies
     out["resident"] = resident_run(reqs, cfg, capacity)
