@@ -205,6 +205,135 @@ __global__ void k_num_big(const int32_t *__restrict__ big, int64_t nbig,
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same aggregation in rank space, from the orientation and its
+// transposition (available once the middle-pivot count has run): the
+// neighbours of rank row r are its out-slots k (N_H(r), ocol[k]) and its
+// in-pairs (u, k) (N_L(r)), and every edge's support sits at its oriented
+// slot, so the symmetric adjacency is not needed.  Rows (out + in entries)
+// longer than BIG_DEG go to a workgroup each.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t rank_row_len(const int64_t *__restrict__ orp,
+                                                const int64_t *__restrict__ in_ptr, int64_t r) {
+    return (orp[r + 1] - orp[r]) + (in_ptr[r + 1] - in_ptr[r]);
+}
+
+// Σ over row r's edges of sup (PASS 1) or of tri(other end) weighted 1 if
+// the edge has support, 3 if not (PASS 2), over the lanes tid, tid + L, ...
+// PASS 1 also packs each in-pair as its lower end with bit 31 set when the
+// edge has no support (in_uw, in in_pair's order), so PASS 2 reads one
+// coalesced word per in-pair instead of gathering the support again.
+template <int PASS>
+__device__ __forceinline__ uint64_t rank_row_sum(int64_t r, int tid, int L,
+                                                 const int64_t *__restrict__ orp,
+                                                 const int32_t *__restrict__ ocol,
+                                                 const int64_t *__restrict__ in_ptr,
+                                                 const uint64_t *__restrict__ in_pair,
+                                                 const uint32_t *__restrict__ osup,
+                                                 uint32_t *__restrict__ in_uw,
+                                                 const uint64_t *__restrict__ tri_r) {
+    uint64_t acc = 0;
+    for (int64_t k = orp[r] + tid; k < orp[r + 1]; k += L) {
+        const uint32_t sp = osup[k];
+        if constexpr (PASS == 1) {
+            acc += sp;
+        } else {
+            const uint64_t t = tri_r[ocol[k]];
+            acc += sp ? t : 3 * t;
+        }
+    }
+    for (int64_t i = in_ptr[r] + tid; i < in_ptr[r + 1]; i += L) {
+        if constexpr (PASS == 1) {
+            const uint64_t pr = in_pair[i];
+            const uint32_t sp = osup[(uint32_t)pr];
+            acc += sp;
+            in_uw[i] = (uint32_t)(pr >> 32) | (sp ? 0u : 0x80000000u);
+        } else {
+            const uint32_t w = in_uw[i];
+            const uint64_t t = tri_r[w & 0x7FFFFFFFu];
+            acc += (w >> 31) ? 3 * t : t;
+        }
+    }
+    return acc;
+}
+
+// PASS 1: tri in rank order (tri_r) and in vertex order (tri).
+// PASS 2: num and tc in vertex order.
+template <int PASS>
+__device__ __forceinline__ void rank_row_finish(int64_t r, uint64_t acc,
+                                                const int32_t *__restrict__ perm,
+                                                uint64_t *__restrict__ tri_r,
+                                                uint64_t *__restrict__ tri,
+                                                const uint64_t *__restrict__ triG,
+                                                const int64_t *__restrict__ vtx_off, int32_t G,
+                                                uint64_t *__restrict__ num,
+                                                double *__restrict__ tcv, uint32_t *__restrict__ err) {
+    const int32_t v = perm[r];
+    if constexpr (PASS == 1) {
+        if (acc & 1) atomicOr(err, 2u);
+        tri_r[r] = acc >> 1;
+        tri[v] = acc >> 1;
+    } else {
+        const uint64_t x = acc + tri_r[r];
+        num[v] = x;
+        tcv[v] = quotient(x, triG[vtx_off ? graph_of(vtx_off, G, v) : 0]);
+    }
+}
+
+template <int PASS>
+__global__ void k_rank_rows(int32_t n, const int64_t *__restrict__ orp,
+                            const int32_t *__restrict__ ocol, const int64_t *__restrict__ in_ptr,
+                            const uint64_t *__restrict__ in_pair, const uint32_t *__restrict__ osup,
+                            uint32_t *__restrict__ in_uw,
+                            const int32_t *__restrict__ perm, uint64_t *__restrict__ tri_r,
+                            uint64_t *__restrict__ tri, const uint64_t *__restrict__ triG,
+                            const int64_t *__restrict__ vtx_off, int32_t G,
+                            uint64_t *__restrict__ num, double *__restrict__ tcv,
+                            uint32_t *__restrict__ err) {
+    const int sub = threadIdx.x % GS;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GS);
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GS; r < n; r += groups) {
+        if (rank_row_len(orp, in_ptr, r) > BIG_DEG) continue;
+        uint64_t acc = rank_row_sum<PASS>(r, sub, GS, orp, ocol, in_ptr, in_pair, osup, in_uw, tri_r);
+        acc = group_sum(acc);
+        if (sub == 0)
+            rank_row_finish<PASS>(r, acc, perm, tri_r, tri, triG, vtx_off, G, num, tcv, err);
+    }
+}
+
+template <int PASS>
+__global__ void k_rank_rows_big(const int32_t *__restrict__ big, int64_t nbig,
+                                const int64_t *__restrict__ orp, const int32_t *__restrict__ ocol,
+                                const int64_t *__restrict__ in_ptr,
+                                const uint64_t *__restrict__ in_pair,
+                                const uint32_t *__restrict__ osup, uint32_t *__restrict__ in_uw,
+                                const int32_t *__restrict__ perm,
+                                uint64_t *__restrict__ tri_r, uint64_t *__restrict__ tri,
+                                const uint64_t *__restrict__ triG,
+                                const int64_t *__restrict__ vtx_off, int32_t G,
+                                uint64_t *__restrict__ num, double *__restrict__ tcv,
+                                uint32_t *__restrict__ err) {
+    __shared__ uint64_t red[16];
+    for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
+        const int64_t r = big[i];
+        uint64_t acc = rank_row_sum<PASS>(r, threadIdx.x, blockDim.x, orp, ocol, in_ptr, in_pair,
+                                          osup, in_uw, tri_r);
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0)
+            rank_row_finish<PASS>(r, acc, perm, tri_r, tri, triG, vtx_off, G, num, tcv, err);
+    }
+}
+
+__global__ void k_rank_big_flags(int32_t n, const int64_t *__restrict__ orp,
+                                 const int64_t *__restrict__ in_ptr, uint32_t *__restrict__ f) {
+    GRID_STRIDE(r, n) f[r] = rank_row_len(orp, in_ptr, r) > BIG_DEG ? 1u : 0u;
+}
+
+__global__ void k_rank_big_write(int32_t n, const uint32_t *__restrict__ f,
+                                 const uint32_t *__restrict__ pos, int32_t *__restrict__ out) {
+    GRID_STRIDE(r, n) if (f[r]) out[pos[r]] = (int32_t)r;
+}
+
 __global__ void k_big_flags(int32_t n, const int64_t *__restrict__ row_ptr, uint32_t *__restrict__ f) {
     GRID_STRIDE(v, n) f[v] = (row_ptr[v + 1] - row_ptr[v]) > BIG_DEG ? 1u : 0u;
 }
@@ -216,11 +345,17 @@ __global__ void k_big_write(int32_t n, const int64_t *__restrict__ row_ptr,
 
 }  // namespace
 
+static tc_status aggregate_rank_space(tc_graph *g, hipStream_t s);
+
 tc_status tc_aggregate(tc_graph *g, hipStream_t s) {
+    // with the transposed orientation at hand, aggregate in rank space; the
+    // symmetric adjacency is then never filled
+    if (g->in_pair) return aggregate_rank_space(g, s);
     const int32_t n = g->n;
     const int64_t m = g->m;
     const int32_t G = g->num_graphs;
     const int64_t nn = n > 0 ? n : 1;
+    TC_TRY(tc_ensure_symmetric(g, s));
     if (!g->esup) TC_TRY(tc_graph_alloc(g, &g->esup, m, s));
     if (!g->flag) TC_TRY(tc_graph_alloc(g, &g->flag, 2 * m, s));
     if (!g->tri) TC_TRY(tc_graph_alloc(g, &g->tri, nn, s));
@@ -273,6 +408,77 @@ tc_status tc_aggregate(tc_graph *g, hipStream_t s) {
     if (nbig > 0) {
         k_num_big<<<(unsigned)(nbig < 65536 ? nbig : 65536), 1024, 0, s>>>(
             big, nbig, g->row_ptr, g->col, g->flag, g->tri, g->triG, voff, G, g->num, g->tcv);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 11, s);
+    return TC_OK;
+}
+
+static tc_status aggregate_rank_space(tc_graph *g, hipStream_t s) {
+    const int32_t n = g->n;
+    const int64_t m = g->m;
+    const int32_t G = g->num_graphs;
+    const int64_t nn = n > 0 ? n : 1;
+    if (!g->esup) TC_TRY(tc_graph_alloc(g, &g->esup, m, s));
+    if (!g->tri) TC_TRY(tc_graph_alloc(g, &g->tri, nn, s));
+    if (!g->num) TC_TRY(tc_graph_alloc(g, &g->num, nn, s));
+    if (!g->tcv) TC_TRY(tc_graph_alloc(g, &g->tcv, nn, s));
+    const int64_t *voff = G > 1 ? g->vtx_off : nullptr;
+    TC_HIP(hipMemsetAsync(g->triG, 0, sizeof(uint64_t) * G, s));
+    if (n == 0) {
+        tc_prof_mark(g, 10, s);
+        tc_prof_mark(g, 11, s);
+        return TC_OK;
+    }
+    tc_scratch tmp(s);
+    uint32_t *f = nullptr, *pos = nullptr, *tot = nullptr;
+    int32_t *big = nullptr;
+    uint64_t *tri_r = nullptr;
+    uint32_t *in_uw = nullptr;
+    TC_TRY(tmp.get(&in_uw, m > 0 ? m : 1));
+    TC_TRY(tmp.get(&f, nn));
+    TC_TRY(tmp.get(&pos, nn));
+    TC_TRY(tmp.get(&tot, 1));
+    TC_TRY(tmp.get(&big, nn));
+    TC_TRY(tmp.get(&tri_r, nn));
+    k_rank_big_flags<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->in_ptr, f);
+    TC_LAUNCHED();
+    TC_TRY(tc_scan_u32(f, pos, n, tot, s));
+    k_rank_big_write<<<grid_for(n), BK, 0, s>>>(n, f, pos, big);
+    TC_LAUNCHED();
+    if (m > 0) {
+        k_scatter_sup<<<grid_for(m), BK, 0, s>>>(m, g->o2e, g->osup, g->esup);
+        TC_LAUNCHED();
+    }
+    uint32_t hbig = 0;
+    TC_HIP(hipMemcpyAsync(&hbig, tot, 4, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    const int64_t nbig = hbig;
+    const unsigned small_grid = grid_for((int64_t)n * GS);
+    const unsigned big_grid = (unsigned)(nbig < 65536 ? (nbig > 0 ? nbig : 1) : 65536);
+    k_rank_rows<1><<<small_grid, BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, g->in_pair, g->osup,
+                                              in_uw, g->perm, tri_r, g->tri, nullptr, voff, G, nullptr,
+                                              nullptr, g->err);
+    TC_LAUNCHED();
+    if (nbig > 0) {
+        k_rank_rows_big<1><<<big_grid, 1024, 0, s>>>(big, nbig, g->orp, g->ocol, g->in_ptr,
+                                                      g->in_pair, g->osup, in_uw, g->perm, tri_r, g->tri,
+                                                      nullptr, voff, G, nullptr, nullptr, g->err);
+        TC_LAUNCHED();
+    }
+    k_tri_sum<<<grid_for(n, BK * 8), BK, 0, s>>>(n, g->tri, voff, G, (unsigned long long *)g->triG);
+    TC_LAUNCHED();
+    k_tri_finish<<<grid_for(G), BK, 0, s>>>(G, g->triG, g->err);
+    TC_LAUNCHED();
+    tc_prof_mark(g, 10, s);
+    k_rank_rows<2><<<small_grid, BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, g->in_pair, g->osup,
+                                              in_uw, g->perm, tri_r, g->tri, g->triG, voff, G, g->num,
+                                              g->tcv, g->err);
+    TC_LAUNCHED();
+    if (nbig > 0) {
+        k_rank_rows_big<2><<<big_grid, 1024, 0, s>>>(big, nbig, g->orp, g->ocol, g->in_ptr,
+                                                      g->in_pair, g->osup, in_uw, g->perm, tri_r, g->tri,
+                                                      g->triG, voff, G, g->num, g->tcv, g->err);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 11, s);

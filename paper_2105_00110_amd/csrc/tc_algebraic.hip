@@ -122,6 +122,9 @@ tc_status tc_alg_numerator(const tc_graph *g, uint64_t *d_num, hipStream_t s) {
     const int32_t n = g->n;
     const int64_t nnz = 2 * g->m;
     if (n == 0) return TC_OK;
+    // the symmetric adjacency is a cache of the handle: filling it does not
+    // change any result the handle reports
+    TC_TRY(tc_ensure_symmetric(const_cast<tc_graph *>(g), s));
     tc_scratch tmp(s);
     uint32_t *tv = nullptr, *f = nullptr, *pos = nullptr, *tot = nullptr, *err = nullptr;
     uint64_t *t = nullptr;

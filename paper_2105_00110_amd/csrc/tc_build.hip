@@ -76,18 +76,35 @@ __global__ void k_unique_flags(const uint64_t *__restrict__ keys, int64_t P, uin
     }
 }
 
+// Writes the canonical edges (first key of every run of equal keys) and, in
+// the same pass, the run [us[u], ue[u]) of the edges whose smaller end is u
+// (edges come sorted by it).  us and ue start zeroed; the end of the last
+// run is set by k_last_run.
 __global__ void k_unique_write(const uint64_t *__restrict__ keys, int64_t P, uint64_t sentinel,
                                int bits, const uint32_t *__restrict__ pos,
-                               int32_t *__restrict__ eu, int32_t *__restrict__ ev) {
+                               int32_t *__restrict__ eu, int32_t *__restrict__ ev,
+                               uint32_t *__restrict__ us, uint32_t *__restrict__ ue) {
     const uint64_t mask = (1ull << bits) - 1;
     GRID_STRIDE(i, P) {
         uint64_t k = keys[i];
-        if (k != sentinel && (i == 0 || keys[i - 1] != k)) {
-            uint32_t p = pos[i];
-            eu[p] = (int32_t)(k >> bits);
-            ev[p] = (int32_t)(k & mask);
+        const uint64_t prev = i > 0 ? keys[i - 1] : sentinel;
+        if (k != sentinel && prev != k) {
+            const uint32_t p = pos[i];
+            const uint32_t u = (uint32_t)(k >> bits), v = (uint32_t)(k & mask);
+            eu[p] = (int32_t)u;
+            ev[p] = (int32_t)v;
+            // prev is the previous distinct key (sentinels sort last)
+            const uint32_t pu = (uint32_t)(prev >> bits);
+            if (i == 0 || pu != u) {
+                us[u] = p;
+                if (i > 0) ue[pu] = p;
+            }
         }
     }
+}
+
+__global__ void k_last_run(int64_t m, const int32_t *__restrict__ eu, uint32_t *__restrict__ ue) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ue[eu[m - 1]] = (uint32_t)m;
 }
 
 // Run boundaries of a sorted id sequence: start/end of each present id.
@@ -520,6 +537,16 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
     TC_TRY(tc_graph_alloc(g, &g->err, 4, s));
     TC_HIP(hipMemsetAsync(g->err, 0, 16, s));
 
+    // runs of the edges by smaller end, filled while the canonical edges are
+    // written
+    int64_t nn = n > 0 ? n : 1;
+    uint32_t *ue = nullptr;
+    TC_TRY(tc_graph_alloc(g, &g->run_us, nn, s));
+    uint32_t *us = g->run_us;
+    TC_TRY(tmp.get(&ue, nn));
+    TC_HIP(hipMemsetAsync(us, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemsetAsync(ue, 0, sizeof(uint32_t) * nn, s));
+
     // -- 1. canonical edges ---------------------------------------------------
     int64_t m = 0;
     if (P > 0) {
@@ -547,7 +574,10 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
         TC_TRY(tc_graph_alloc(g, &g->eu, m, s));
         TC_TRY(tc_graph_alloc(g, &g->ev, m, s));
         if (m > 0) {
-            k_unique_write<<<grid_for(P), BK, 0, s>>>(keys, P, sentinel, bits, pos, g->eu, g->ev);
+            k_unique_write<<<grid_for(P), BK, 0, s>>>(keys, P, sentinel, bits, pos, g->eu, g->ev,
+                                                      us, ue);
+            TC_LAUNCHED();
+            k_last_run<<<1, 64, 0, s>>>(m, g->eu, ue);
             TC_LAUNCHED();
         }
     } else {
@@ -556,37 +586,25 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
     }
     g->m = m;
 
-    // -- 2. symmetric CSR -------------------------------------------------------
+    // -- 2. degrees and the symmetric row offsets ------------------------------
+    // The adjacency itself (col / sym2e) is filled only when a consumer
+    // needs it (tc_ensure_symmetric).
     TC_TRY(tc_graph_alloc(g, &g->row_ptr, (int64_t)n + 1, s));
-    TC_TRY(tc_graph_alloc(g, &g->col, 2 * m, s));
-    TC_TRY(tc_graph_alloc(g, &g->sym2e, 2 * m, s));
-    uint32_t *us = nullptr, *ue = nullptr, *ls = nullptr, *le = nullptr, *deg32 = nullptr;
+    // the count of edges by larger end: the runs of ev sorted (keys only)
+    uint32_t *deg32 = nullptr, *ls = nullptr, *le = nullptr;
     int64_t *deg64 = nullptr;
-    int64_t nn = n > 0 ? n : 1;
-    TC_TRY(tmp.get(&us, nn));
-    TC_TRY(tmp.get(&ue, nn));
-    TC_TRY(tmp.get(&ls, nn));
-    TC_TRY(tmp.get(&le, nn));
     TC_TRY(tmp.get(&deg32, nn));
     TC_TRY(tmp.get(&deg64, nn));
-    TC_HIP(hipMemsetAsync(us, 0, sizeof(uint32_t) * nn, s));
-    TC_HIP(hipMemsetAsync(ue, 0, sizeof(uint32_t) * nn, s));
+    TC_TRY(tmp.get(&ls, nn));
+    TC_TRY(tmp.get(&le, nn));
     TC_HIP(hipMemsetAsync(ls, 0, sizeof(uint32_t) * nn, s));
     TC_HIP(hipMemsetAsync(le, 0, sizeof(uint32_t) * nn, s));
-    uint32_t *tkey = nullptr, *tval = nullptr;
     if (m > 0) {
-        uint32_t *tkey2 = nullptr, *tval2 = nullptr;
-        TC_TRY(tmp.get(&tkey, m));
-        TC_TRY(tmp.get(&tval, m));
-        TC_TRY(tmp.get(&tkey2, m));
-        TC_TRY(tmp.get(&tval2, m));
-        TC_HIP(hipMemcpyAsync(tkey, g->ev, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
-        k_iota<<<grid_for(m), BK, 0, s>>>(tval, m);
-        TC_LAUNCHED();
-        TC_TRY(tc_sort_u32_u32(&tkey, &tval, &tkey2, &tval2, m, bits, s));
-        k_runs<<<grid_for(m), BK, 0, s>>>(GetI32{g->eu}, m, us, ue);
-        TC_LAUNCHED();
-        k_runs<<<grid_for(m), BK, 0, s>>>(GetU32{tkey}, m, ls, le);
+        uint32_t *lk = nullptr, *lk2 = nullptr;
+        TC_TRY(tmp.get(&lk, m));
+        TC_TRY(tmp.get(&lk2, m));
+        TC_TRY(tc_sort_u32_from((const uint32_t *)g->ev, &lk, &lk2, m, bits, s));
+        k_runs<<<grid_for(m), BK, 0, s>>>(GetU32{lk}, m, ls, le);
         TC_LAUNCHED();
     }
     if (n > 0) {
@@ -595,14 +613,6 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
         TC_TRY(tc_scan_i64(deg64, g->row_ptr, n, g->row_ptr + n, s));
     } else {
         TC_HIP(hipMemsetAsync(g->row_ptr, 0, sizeof(int64_t), s));
-    }
-    if (m > 0) {
-        k_fill_lower<<<grid_for(m), BK, 0, s>>>(m, tkey, tval, ls, g->row_ptr, g->eu, g->col,
-                                                g->sym2e);
-        TC_LAUNCHED();
-        k_fill_upper<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, us, ls, le, g->row_ptr, g->col,
-                                                g->sym2e);
-        TC_LAUNCHED();
     }
 
     tc_prof_mark(g, 1, s);
@@ -663,5 +673,41 @@ static tc_status orient_sorted(tc_graph *g, hipStream_t s) {
     k_run_len64<<<grid_for(n), BK, 0, s>>>(n, rs, re, dplus, d_max);
     TC_LAUNCHED();
     TC_TRY(tc_scan_i64(dplus, g->orp, n, g->orp + n, s));
+    return TC_OK;
+}
+
+// ---------------------------------------------------------------------------
+tc_status tc_ensure_symmetric(tc_graph *g, hipStream_t s) {
+    if (g->col) return TC_OK;
+    const int32_t n = g->n;
+    const int64_t m = g->m;
+    const int64_t nn = n > 0 ? n : 1;
+    TC_TRY(tc_graph_alloc(g, &g->col, 2 * m, s));
+    TC_TRY(tc_graph_alloc(g, &g->sym2e, 2 * m, s));
+    if (m == 0) return TC_OK;
+    // the transposition: canonical edges sorted by their larger end, and
+    // the run of every vertex in that order
+    tc_scratch tmp(s);
+    uint32_t *tkey = nullptr, *tval = nullptr, *tkey2 = nullptr, *tval2 = nullptr;
+    uint32_t *ls = nullptr, *le = nullptr;
+    TC_TRY(tmp.get(&tkey, m));
+    TC_TRY(tmp.get(&tval, m));
+    TC_TRY(tmp.get(&tkey2, m));
+    TC_TRY(tmp.get(&tval2, m));
+    TC_TRY(tmp.get(&ls, nn));
+    TC_TRY(tmp.get(&le, nn));
+    TC_HIP(hipMemsetAsync(ls, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemsetAsync(le, 0, sizeof(uint32_t) * nn, s));
+    TC_HIP(hipMemcpyAsync(tkey, g->ev, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
+    k_iota<<<grid_for(m), BK, 0, s>>>(tval, m);
+    TC_LAUNCHED();
+    TC_TRY(tc_sort_u32_u32(&tkey, &tval, &tkey2, &tval2, m, g->bits, s));
+    k_runs<<<grid_for(m), BK, 0, s>>>(GetU32{tkey}, m, ls, le);
+    TC_LAUNCHED();
+    k_fill_lower<<<grid_for(m), BK, 0, s>>>(m, tkey, tval, ls, g->row_ptr, g->eu, g->col, g->sym2e);
+    TC_LAUNCHED();
+    k_fill_upper<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->run_us, ls, le, g->row_ptr, g->col,
+                                            g->sym2e);
+    TC_LAUNCHED();
     return TC_OK;
 }

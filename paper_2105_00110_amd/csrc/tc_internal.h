@@ -88,6 +88,9 @@ tc_status tc_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total
 // The sorted data ends in *keys / *vals: the pointers are swapped with the
 // tmp pointers when the pass count is odd, so callers free both buffers.
 tc_status tc_sort_u64(uint64_t **keys, uint64_t **tmp_keys, int64_t n, int bits, hipStream_t s);
+// keys only, the first pass reading src (left unchanged); the result is in *keys
+tc_status tc_sort_u32_from(const uint32_t *src, uint32_t **keys, uint32_t **tmp_keys, int64_t n,
+                           int bits, hipStream_t s);
 tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s);
 tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,
@@ -112,8 +115,11 @@ struct tc_graph {
     int32_t *eu = nullptr, *ev = nullptr;           // [m]
     // symmetric CSR in original ids, rows sorted by id
     int64_t *row_ptr = nullptr;                     // [n+1]
-    int32_t *col = nullptr;                         // [2m]
+    int32_t *col = nullptr;                         // [2m] (filled on demand)
     uint32_t *sym2e = nullptr;                      // [2m] canonical edge of each slot
+    // kept from the build so that col / sym2e can be filled on demand: the
+    // first canonical edge whose smaller end is v
+    uint32_t *run_us = nullptr;                     // [n]
     // degree order: perm[r] = vertex of rank r, rank[v]
     int32_t *rank = nullptr, *perm = nullptr;       // [n]
     // oriented CSR over ranks: row r holds the ranks above r, ascending
@@ -170,6 +176,9 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
 tc_status tc_orient(tc_graph *g, hipStream_t s);
 tc_status tc_count(tc_graph *g, const tc_tuning *t, hipStream_t s);
 tc_status tc_aggregate(tc_graph *g, hipStream_t s);
+// Fills the symmetric adjacency col / sym2e from what the build kept
+// (once per handle; no-op when filled).  tc_build.hip.
+tc_status tc_ensure_symmetric(tc_graph *g, hipStream_t s);
 tc_status tc_alg_numerator(const tc_graph *g, uint64_t *d_num, hipStream_t s);  // tc_algebraic.hip
 tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s);
 tc_status tc_mid_prepare(tc_graph *g, hipStream_t s);

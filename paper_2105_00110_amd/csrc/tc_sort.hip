@@ -150,9 +150,16 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
     }
 }
 
+// src, when given, is read by the first pass in place of *keys (which then
+// needs no contents); *keys and *tkeys are ping-pong buffers as usual.
 template <typename K, typename V, bool HAS_VAL>
-tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bits, hipStream_t s) {
+tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bits, hipStream_t s,
+                     const K *src = nullptr) {
     if (n < 0 || bits < 0 || bits > (int)(8 * sizeof(K))) return TC_ERR_INVALID_ARG;
+    if (src && (n <= 1 || bits == 0)) {
+        if (n > 0) TC_HIP(hipMemcpyAsync(*keys, src, sizeof(K) * n, hipMemcpyDeviceToDevice, s));
+        return TC_OK;
+    }
     if (n <= 1 || bits == 0) return TC_OK;
     if (n >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
     int64_t tiles = tc_div_up(n, SORT_TILE);
@@ -160,11 +167,12 @@ tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bi
     uint32_t *counts = nullptr;
     TC_TRY(tmp.get(&counts, tiles * RADIX));
     for (int shift = 0; shift < bits; shift += RB) {
-        k_radix_hist<K><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(*keys, n, shift, counts, tiles);
+        const K *in = (src && shift == 0) ? src : *keys;
+        k_radix_hist<K><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(in, n, shift, counts, tiles);
         TC_LAUNCHED();
         TC_TRY(tc_scan_u32(counts, counts, tiles * RADIX, nullptr, s));
         k_radix_scatter<K, V, HAS_VAL><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(
-            *keys, HAS_VAL ? *vals : nullptr, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift,
+            in, HAS_VAL ? *vals : nullptr, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift,
             counts, tiles);
         TC_LAUNCHED();
         K *tk = *keys;
@@ -184,6 +192,12 @@ tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bi
 tc_status tc_sort_u64(uint64_t **keys, uint64_t **tmp_keys, int64_t n, int bits, hipStream_t s) {
     uint32_t *nv = nullptr, *ntv = nullptr;
     return radix_sort<uint64_t, uint32_t, false>(keys, &nv, tmp_keys, &ntv, n, bits, s);
+}
+
+tc_status tc_sort_u32_from(const uint32_t *src, uint32_t **keys, uint32_t **tmp_keys, int64_t n,
+                           int bits, hipStream_t s) {
+    uint32_t *nv = nullptr, *ntv = nullptr;
+    return radix_sort<uint32_t, uint32_t, false>(keys, &nv, tmp_keys, &ntv, n, bits, s, src);
 }
 
 tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
