@@ -222,7 +222,7 @@ void free_graph_arrays(tc_graph *g, hipStream_t s) {
                     g->orp,  g->ocol, g->o2e,     g->osup, g->esup,  g->flag, g->tri,
                     g->num,  g->tcv,  g->triG,    g->vtx_off, g->err, g->bin_rows,
                     g->in_ptr, g->in_pair, g->rowbase, g->hitbits, g->orow,
-                    g->run_us};
+                    g->run_us, g->lt_key, g->lt_val};
     for (void *p : arrs) tc_dev_free(p, s);
 }
 

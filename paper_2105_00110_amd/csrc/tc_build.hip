@@ -218,11 +218,14 @@ __global__ void k_run_len64(int32_t n, const uint32_t *__restrict__ s, const uin
 
 // ---------------------------------------------------------------------------
 // Orientation without a global sort (every row at most SEG_MAX entries):
-//   pass A  each canonical edge is written once, into a bucket of its
+//   pass A  each canonical edge is written once, into the bucket of its
 //           lower-ordered endpoint x: (rank of the other end, edge id) at
-//           tmp[row_ptr[x] + slot], slot from an atomic cursor per vertex
-//           (a bucket never outgrows x's symmetric row, and it receives at
-//           most d+(x) entries, which bounds the contention per cursor);
+//           tmp[row_ptr[x] + slot] (a bucket never outgrows x's symmetric
+//           row).  The edges are visited twice, in canonical order (runs of
+//           the smaller id u) taking those with x = u, and ordered by the
+//           larger id (runs of v) taking those with x = v, so a wavefront's
+//           entries for one bucket are neighbours and take their slots with
+//           one atomic on x's cursor, and are stored side by side;
 //   pass B  d+ = the cursors, scanned into the offsets of the rank rows;
 //           each bucket is put in order by rank in LDS and written to
 //           ocol/o2e, with the row of every slot in orow.
@@ -230,44 +233,87 @@ __global__ void k_run_len64(int32_t n, const uint32_t *__restrict__ s, const uin
 constexpr int SEG_MAX = 4096;
 constexpr int SEG_WAVE = 64;  // buckets up to this many entries: one wavefront
 
-__global__ void k_orient_place(int64_t m, const int32_t *__restrict__ eu,
-                               const int32_t *__restrict__ ev, const int32_t *__restrict__ rank,
-                               const int64_t *__restrict__ row_ptr, uint32_t *__restrict__ cursor,
-                               uint64_t *__restrict__ tbuf) {
-    // Canonical edges come sorted by their smaller id, so neighbouring lanes
-    // often write to the same bucket: each run of equal buckets in the
-    // wavefront takes its slots with one atomic, by its first lane.
+// Lanes hold consecutive elements of a sequence sorted by x (x is the same
+// for neighbouring lanes of one run); the active ones store their entry in
+// x's bucket, each run's active lanes taking consecutive slots with one
+// atomic.
+__device__ __forceinline__ void place_runs(bool valid, int32_t x, bool active, uint64_t entry,
+                                           const int64_t *__restrict__ row_ptr,
+                                           uint32_t *__restrict__ cursor,
+                                           uint64_t *__restrict__ tbuf) {
+    const int lane = __lane_id();
+    const int32_t prev = __shfl_up(x, 1, TC_WAVE);
+    const bool head = valid && (lane == 0 || prev != x);
+    const uint64_t heads = __ballot(head);
+    const uint64_t acts = __ballot(valid && active);
+    const uint64_t upto = (2ull << lane) - 1;             // lanes 0..lane
+    const uint64_t below = (1ull << lane) - 1;            // lanes 0..lane-1
+    const uint64_t mine = heads & upto;
+    const int hl = mine ? 63 - __clzll((long long)mine) : 0;  // head of this lane's run
+    uint32_t base = 0;
+    if (head) {
+        const uint64_t later = heads & ~upto;
+        const uint64_t run = (later ? ((later & (0 - later)) - 1) : ~0ull) & ~below;
+        const uint32_t cnt = (uint32_t)__popcll(acts & run);
+        if (cnt) base = atomicAdd(&cursor[x], cnt);
+    }
+    base = __shfl(base, hl, TC_WAVE);
+    if (valid && active) {
+        const uint64_t before = acts & below & ~((1ull << hl) - 1);  // active lanes in [hl, lane)
+        tbuf[row_ptr[x] + base + (uint32_t)__popcll(before)] = entry;
+    }
+}
+
+// Canonical order: edge e = (u, v), u < v; x = u when u is ordered first.
+// Also records the rank of u per edge for the second pass.
+__global__ void k_place_by_smaller(int64_t m, const int32_t *__restrict__ eu,
+                                   const int32_t *__restrict__ ev, const int32_t *__restrict__ rank,
+                                   const int64_t *__restrict__ row_ptr,
+                                   uint32_t *__restrict__ cursor, uint64_t *__restrict__ tbuf,
+                                   uint32_t *__restrict__ rank_u) {
     const int lane = __lane_id();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; e0 < m; e0 += stride) {
         const int64_t e = e0 + lane;
         const bool valid = e < m;
-        int32_t x = -1;
-        uint32_t other = 0;
+        int32_t u = -1;
+        bool active = false;
+        uint64_t entry = 0;
         if (valid) {
-            const int32_t u = eu[e], v = ev[e];
-            const int32_t a = rank[u], b = rank[v];
-            x = a < b ? u : v;
-            other = (uint32_t)(a < b ? b : a);
+            u = eu[e];
+            const uint32_t a = (uint32_t)rank[u], b = (uint32_t)rank[ev[e]];
+            rank_u[e] = a;
+            active = a < b;
+            entry = ((uint64_t)b << 32) | (uint32_t)e;
         }
-        const int32_t prev = __shfl_up(x, 1, TC_WAVE);
-        const bool head = valid && (lane == 0 || prev != x);
-        const uint64_t heads = __ballot(head);
-        const uint64_t valids = __ballot(valid);
-        uint32_t base = 0;
-        if (head) {
-            const uint64_t later = heads & ~((2ull << lane) - 1);  // heads above this lane
-            const int end = later ? __ffsll((long long)later) - 1 : 64 - __clzll((long long)valids);
-            base = atomicAdd(&cursor[x], (uint32_t)(end - lane));
-        }
-        // the head of this lane's run: the highest head at or below the lane
-        const uint64_t mine = heads & ((2ull << lane) - 1);
-        const int hl = mine ? 63 - __clzll((long long)mine) : 0;
-        base = __shfl(base, hl, TC_WAVE);
+        place_runs(valid, u, active, entry, row_ptr, cursor, tbuf);
+    }
+}
+
+// Edges ordered by the larger id v (key v, value e): x = v when v is
+// ordered first.
+__global__ void k_place_by_larger(int64_t m, const uint32_t *__restrict__ lt_key,
+                                  const uint32_t *__restrict__ lt_val,
+                                  const int32_t *__restrict__ rank,
+                                  const uint32_t *__restrict__ rank_u,
+                                  const int64_t *__restrict__ row_ptr,
+                                  uint32_t *__restrict__ cursor, uint64_t *__restrict__ tbuf) {
+    const int lane = __lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; j0 < m; j0 += stride) {
+        const int64_t j = j0 + lane;
+        const bool valid = j < m;
+        int32_t v = -1;
+        bool active = false;
+        uint64_t entry = 0;
         if (valid) {
-            // one 8-byte store per entry: (rank of the other end << 32) | edge
-            tbuf[row_ptr[x] + base + (uint32_t)(lane - hl)] = ((uint64_t)other << 32) | (uint32_t)e;
+            v = (int32_t)lt_key[j];
+            const uint32_t e = lt_val[j];
+            const uint32_t a = rank_u[e], b = (uint32_t)rank[v];
+            active = b < a;
+            entry = ((uint64_t)a << 32) | e;
         }
+        place_runs(valid, v, active, entry, row_ptr, cursor, tbuf);
     }
 }
 
@@ -285,37 +331,58 @@ __global__ void k_dplus_by_rank(int32_t n, const uint32_t *__restrict__ cursor,
     if (__lane_id() == 0 && mx) atomicMax(dmax, mx);
 }
 
-// One wavefront per vertex whose bucket holds 1..SEG_WAVE entries: each
-// lane places its entry by the number of smaller keys (keys of a bucket are
-// distinct ranks).
-__global__ __launch_bounds__(256) void k_orient_wave(
-    int32_t n, const int64_t *__restrict__ row_ptr, const uint32_t *__restrict__ cursor,
-    const int32_t *__restrict__ rank, const int64_t *__restrict__ orp,
-    const uint64_t *__restrict__ tbuf, int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
-    int32_t *__restrict__ orow) {
-    __shared__ uint32_t sk[4][SEG_WAVE];
+// Buckets of lo < d <= GL entries (GL <= SEG_WAVE), GL lanes each: every
+// wavefront reads the sizes of 64 consecutive vertices, takes those of its
+// class from the ballot, 64 / GL at a time, and each lane places its entry by
+// the number of smaller keys in its group (keys of a bucket are distinct
+// ranks).  The grid strides over the vertices, so there is no wavefront per
+// vertex to dispatch.
+template <int GL>
+__global__ __launch_bounds__(256) void k_orient_small(
+    int32_t n, uint32_t lo, const int64_t *__restrict__ row_ptr,
+    const uint32_t *__restrict__ cursor, const int32_t *__restrict__ rank,
+    const int64_t *__restrict__ orp, const uint64_t *__restrict__ tbuf,
+    int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e, int32_t *__restrict__ orow) {
+    static_assert(GL <= SEG_WAVE && TC_WAVE % GL == 0, "group size");
+    constexpr int GPW = TC_WAVE / GL;
+    __shared__ uint32_t sk[4][TC_WAVE];
     const int wv = threadIdx.x / TC_WAVE;
     const int lane = __lane_id();
-    const int64_t waves = (int64_t)gridDim.x * 4;
-    for (int64_t x = (int64_t)blockIdx.x * 4 + wv; x < n; x += waves) {
-        const int d = (int)cursor[x];
-        if (d == 0 || d > SEG_WAVE) continue;
-        const int64_t b = row_ptr[x];
-        uint32_t key = 0xFFFFFFFFu, val = 0;
-        if (lane < d) {
-            const uint64_t w = tbuf[b + lane];
-            key = (uint32_t)(w >> 32);
-            val = (uint32_t)w;
-        }
-        sk[wv][lane] = key;
-        int pos = 0;
-        for (int j = 0; j < d; ++j) pos += sk[wv][j] < key ? 1 : 0;
-        if (lane < d) {
-            const int32_t rx = rank[x];
-            const int64_t k = orp[rx] + pos;
-            ocol[k] = (int32_t)key;
-            o2e[k] = val;
-            orow[k] = rx;
+    const int grp = lane / GL, sl = lane % GL;
+    uint32_t *gsk = &sk[wv][grp * GL];
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    for (int64_t x0 = ((int64_t)blockIdx.x * 4 + wv) * TC_WAVE; x0 < n; x0 += nwaves * TC_WAVE) {
+        const int64_t xl = x0 + lane;
+        const uint32_t dl = xl < n ? cursor[xl] : 0u;
+        uint64_t mask = __ballot(dl > lo && dl <= (uint32_t)GL);
+        while (mask) {
+            // this group's vertex: the grp-th set bit of the mask, if any
+            uint64_t mm = mask;
+            for (int q = 0; q < grp && mm; ++q) mm &= mm - 1;
+            const bool has = mm != 0;
+            const int j = has ? __ffsll((long long)mm) - 1 : 0;
+            for (int q = 0; q < GPW && mask; ++q) mask &= mask - 1;
+            const int d = (int)__shfl(dl, j, TC_WAVE);
+            const int64_t x = x0 + j;
+            const bool mine = has && sl < d;
+            uint32_t key = 0xFFFFFFFFu, val = 0;
+            if (mine) {
+                const uint64_t w = tbuf[row_ptr[x] + sl];
+                key = (uint32_t)(w >> 32);
+                val = (uint32_t)w;
+            }
+            gsk[sl] = key;
+            __builtin_amdgcn_wave_barrier();
+            if (mine) {
+                int pos = 0;
+                for (int t = 0; t < d; ++t) pos += gsk[t] < key ? 1 : 0;
+                const int32_t rx = rank[x];
+                const int64_t k = orp[rx] + pos;
+                ocol[k] = (int32_t)key;
+                o2e[k] = val;
+                orow[k] = rx;
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
@@ -442,7 +509,22 @@ static tc_status compact_vertices(int32_t n, uint32_t *f, int32_t *out, uint32_t
     return TC_OK;
 }
 
+static tc_status orient_impl(tc_graph *g, hipStream_t s);
+
 tc_status tc_orient(tc_graph *g, hipStream_t s) {
+    const tc_status st = orient_impl(g, s);
+    // the order by larger id served the placement only
+    if (g->lt_key) {
+        tc_dev_free(g->lt_key, s);
+        tc_dev_free(g->lt_val, s);
+        g->lt_key = nullptr;
+        g->lt_val = nullptr;
+        g->bytes -= 2 * sizeof(uint32_t) * (size_t)(g->m > 0 ? g->m : 1);
+    }
+    return st;
+}
+
+static tc_status orient_impl(tc_graph *g, hipStream_t s) {
     const int32_t n = g->n;
     const int64_t m = g->m;
     int64_t nn = n > 0 ? n : 1;
@@ -474,8 +556,16 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     TC_HIP(hipMemsetAsync(info, 0, 16, s));
     TC_HIP(hipMemsetAsync(cursor, 0, sizeof(uint32_t) * nn, s));
     // pass A: buckets of the lower-ordered endpoints
-    k_orient_place<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->rank, g->row_ptr, cursor, tbuf);
-    TC_LAUNCHED();
+    {
+        uint32_t *rank_u = nullptr;
+        TC_TRY(tmp.get(&rank_u, m));
+        k_place_by_smaller<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->rank, g->row_ptr, cursor,
+                                                      tbuf, rank_u);
+        TC_LAUNCHED();
+        k_place_by_larger<<<grid_for(m), BK, 0, s>>>(m, g->lt_key, g->lt_val, g->rank, rank_u,
+                                                     g->row_ptr, cursor, tbuf);
+        TC_LAUNCHED();
+    }
     k_dplus_by_rank<<<grid_for(n) < 4096 ? grid_for(n) : 4096, BK, 0, s>>>(n, cursor, g->rank, dplus,
                                                                           info);
     TC_LAUNCHED();
@@ -507,9 +597,22 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     }
     TC_TRY(tc_scan_i64(dplus, g->orp, n, g->orp + n, s));
     // pass B: each bucket in rank order
-    k_orient_wave<<<(unsigned)tc_div_up(n, 4), BK, 0, s>>>(n, g->row_ptr, cursor, g->rank, g->orp,
-                                                         tbuf, g->ocol, g->o2e, g->orow);
-    TC_LAUNCHED();
+    {
+        const int64_t want = tc_div_up(n, 4 * TC_WAVE);
+        const unsigned grid = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+        k_orient_small<8><<<grid, BK, 0, s>>>(n, 0, g->row_ptr, cursor, g->rank, g->orp, tbuf,
+                                              g->ocol, g->o2e, g->orow);
+        TC_LAUNCHED();
+        k_orient_small<16><<<grid, BK, 0, s>>>(n, 8, g->row_ptr, cursor, g->rank, g->orp, tbuf,
+                                               g->ocol, g->o2e, g->orow);
+        TC_LAUNCHED();
+        k_orient_small<32><<<grid, BK, 0, s>>>(n, 16, g->row_ptr, cursor, g->rank, g->orp, tbuf,
+                                               g->ocol, g->o2e, g->orow);
+        TC_LAUNCHED();
+        k_orient_small<64><<<grid, BK, 0, s>>>(n, 32, g->row_ptr, cursor, g->rank, g->orp, tbuf,
+                                               g->ocol, g->o2e, g->orow);
+        TC_LAUNCHED();
+    }
     if (nmid > 0) {
         const int64_t blocks = tc_div_up(nmid, 4);
         k_orient_mid<<<(unsigned)(blocks < 1048576 ? blocks : 1048576), BK, 0, s>>>(
@@ -590,7 +693,8 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
     // The adjacency itself (col / sym2e) is filled only when a consumer
     // needs it (tc_ensure_symmetric).
     TC_TRY(tc_graph_alloc(g, &g->row_ptr, (int64_t)n + 1, s));
-    // the count of edges by larger end: the runs of ev sorted (keys only)
+    // the canonical edges ordered by their larger end (kept for the
+    // orientation), whose runs count the edges by larger end
     uint32_t *deg32 = nullptr, *ls = nullptr, *le = nullptr;
     int64_t *deg64 = nullptr;
     TC_TRY(tmp.get(&deg32, nn));
@@ -600,11 +704,20 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
     TC_HIP(hipMemsetAsync(ls, 0, sizeof(uint32_t) * nn, s));
     TC_HIP(hipMemsetAsync(le, 0, sizeof(uint32_t) * nn, s));
     if (m > 0) {
-        uint32_t *lk = nullptr, *lk2 = nullptr;
-        TC_TRY(tmp.get(&lk, m));
+        uint32_t *lk2 = nullptr, *lv2 = nullptr;
+        TC_TRY(tc_graph_alloc(g, &g->lt_key, m, s));
+        TC_TRY(tc_graph_alloc(g, &g->lt_val, m, s));
         TC_TRY(tmp.get(&lk2, m));
-        TC_TRY(tc_sort_u32_from((const uint32_t *)g->ev, &lk, &lk2, m, bits, s));
-        k_runs<<<grid_for(m), BK, 0, s>>>(GetU32{lk}, m, ls, le);
+        TC_TRY(tmp.get(&lv2, m));
+        uint32_t *lk = g->lt_key, *lv = g->lt_val;
+        TC_TRY(tc_sort_u32_index((const uint32_t *)g->ev, &lk, &lv, &lk2, &lv2, m, bits, s));
+        if (lk != g->lt_key) {  // the result is in the scratch pair: swap ownership
+            tmp.exchange(lk, g->lt_key);
+            tmp.exchange(lv, g->lt_val);
+            g->lt_key = lk;
+            g->lt_val = lv;
+        }
+        k_runs<<<grid_for(m), BK, 0, s>>>(GetU32{g->lt_key}, m, ls, le);
         TC_LAUNCHED();
     }
     if (n > 0) {

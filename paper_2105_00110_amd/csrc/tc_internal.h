@@ -69,6 +69,14 @@ struct tc_scratch {
         if (r == TC_OK) ptrs[n++] = (void *)*p;
         return r;
     }
+    // p, allocated here, passes to the caller; q (same size) is freed in its place
+    void exchange(void *p, void *q) {
+        for (int i = 0; i < n; ++i)
+            if (ptrs[i] == p) {
+                ptrs[i] = q;
+                return;
+            }
+    }
     ~tc_scratch() {
         for (int i = n - 1; i >= 0; --i) tc_dev_free(ptrs[i], s);
     }
@@ -91,6 +99,11 @@ tc_status tc_sort_u64(uint64_t **keys, uint64_t **tmp_keys, int64_t n, int bits,
 // keys only, the first pass reading src (left unchanged); the result is in *keys
 tc_status tc_sort_u32_from(const uint32_t *src, uint32_t **keys, uint32_t **tmp_keys, int64_t n,
                            int bits, hipStream_t s);
+// keys from src (left unchanged), values the input positions 0..n-1: the
+// stable sorting permutation of src; the result is in *keys / *vals
+tc_status tc_sort_u32_index(const uint32_t *src, uint32_t **keys, uint32_t **vals,
+                            uint32_t **tmp_keys, uint32_t **tmp_vals, int64_t n, int bits,
+                            hipStream_t s);
 tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s);
 tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,
@@ -120,6 +133,9 @@ struct tc_graph {
     // kept from the build so that col / sym2e can be filled on demand: the
     // first canonical edge whose smaller end is v
     uint32_t *run_us = nullptr;                     // [n]
+    // from the build to the orientation only: the canonical edges ordered by
+    // their larger end (key = ev, val = edge)
+    uint32_t *lt_key = nullptr, *lt_val = nullptr;  // [m]
     // degree order: perm[r] = vertex of rank r, rank[v]
     int32_t *rank = nullptr, *perm = nullptr;       // [n]
     // oriented CSR over ranks: row r holds the ranks above r, ascending

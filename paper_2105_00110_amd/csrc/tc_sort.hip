@@ -83,7 +83,8 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
         int64_t i = wbase + it * TC_WAVE + lane;
         bool valid = i < n;
         key[it] = valid ? kin[i] : (K)0;
-        if constexpr (HAS_VAL) val[it] = valid ? vin[i] : (V)0;
+        // no value array: the value is the element's index
+        if constexpr (HAS_VAL) val[it] = valid ? (vin ? vin[i] : (V)i) : (V)0;
     }
 #pragma unroll
     for (int it = 0; it < SORT_ITEMS; ++it) {
@@ -151,16 +152,17 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
 }
 
 // src, when given, is read by the first pass in place of *keys (which then
-// needs no contents); *keys and *tkeys are ping-pong buffers as usual.
+// needs no contents); with iota the first pass takes each element's index as
+// its value in place of *vals.  *keys and *tkeys are ping-pong buffers as
+// usual.  With either, at least one pass runs, so the result is always
+// written to the buffers.
 template <typename K, typename V, bool HAS_VAL>
 tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bits, hipStream_t s,
-                     const K *src = nullptr) {
+                     const K *src = nullptr, bool iota = false) {
     if (n < 0 || bits < 0 || bits > (int)(8 * sizeof(K))) return TC_ERR_INVALID_ARG;
-    if (src && (n <= 1 || bits == 0)) {
-        if (n > 0) TC_HIP(hipMemcpyAsync(*keys, src, sizeof(K) * n, hipMemcpyDeviceToDevice, s));
-        return TC_OK;
-    }
-    if (n <= 1 || bits == 0) return TC_OK;
+    const bool fresh = src != nullptr || iota;
+    if (n == 0 || (!fresh && (n <= 1 || bits == 0))) return TC_OK;
+    if (fresh && bits == 0) bits = 1;  // keys below 2^0 are all zero: one pass keeps the order
     if (n >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
     int64_t tiles = tc_div_up(n, SORT_TILE);
     tc_scratch tmp(s);
@@ -168,12 +170,12 @@ tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bi
     TC_TRY(tmp.get(&counts, tiles * RADIX));
     for (int shift = 0; shift < bits; shift += RB) {
         const K *in = (src && shift == 0) ? src : *keys;
+        const V *vin = (HAS_VAL && !(iota && shift == 0)) ? *vals : nullptr;
         k_radix_hist<K><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(in, n, shift, counts, tiles);
         TC_LAUNCHED();
         TC_TRY(tc_scan_u32(counts, counts, tiles * RADIX, nullptr, s));
         k_radix_scatter<K, V, HAS_VAL><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(
-            in, HAS_VAL ? *vals : nullptr, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift,
-            counts, tiles);
+            in, vin, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift, counts, tiles);
         TC_LAUNCHED();
         K *tk = *keys;
         *keys = *tkeys;
@@ -198,6 +200,13 @@ tc_status tc_sort_u32_from(const uint32_t *src, uint32_t **keys, uint32_t **tmp_
                            int bits, hipStream_t s) {
     uint32_t *nv = nullptr, *ntv = nullptr;
     return radix_sort<uint32_t, uint32_t, false>(keys, &nv, tmp_keys, &ntv, n, bits, s, src);
+}
+
+tc_status tc_sort_u32_index(const uint32_t *src, uint32_t **keys, uint32_t **vals,
+                            uint32_t **tmp_keys, uint32_t **tmp_vals, int64_t n, int bits,
+                            hipStream_t s) {
+    return radix_sort<uint32_t, uint32_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s, src,
+                                                true);
 }
 
 tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
