@@ -65,27 +65,14 @@ static inline unsigned grid_for(int64_t n, int block = BK) {
 // ---------------------------------------------------------------------------
 // Transposed orientation
 // ---------------------------------------------------------------------------
-__global__ void k_slot_keys(int64_t m, const int32_t *__restrict__ orow,
-                            const int32_t *__restrict__ ocol, uint32_t *__restrict__ key,
-                            uint64_t *__restrict__ val) {
-    GRID_STRIDE(k, m) {
-        key[k] = (uint32_t)ocol[k];
-        val[k] = ((uint64_t)(uint32_t)orow[k] << 32) | (uint64_t)k;
-    }
-}
-
-__global__ void k_in_runs(const uint32_t *__restrict__ key, int64_t len, uint32_t *__restrict__ start,
-                          uint32_t *__restrict__ end) {
-    GRID_STRIDE(i, len) {
-        const uint32_t x = key[i];
-        if (i == 0 || key[i - 1] != x) start[x] = (uint32_t)i;
-        if (i == len - 1 || key[i + 1] != x) end[x] = (uint32_t)(i + 1);
-    }
-}
-
-__global__ void k_in_len(int32_t n, const uint32_t *__restrict__ s, const uint32_t *__restrict__ e,
+// Number of lower-ordered neighbours of rank r: its degree less d+(r).
+__global__ void k_in_len(int32_t n, const int32_t *__restrict__ perm,
+                         const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ orp,
                          int64_t *__restrict__ len) {
-    GRID_STRIDE(x, n) len[x] = e[x] - s[x];
+    GRID_STRIDE(r, n) {
+        const int32_t v = perm[r];
+        len[r] = (row_ptr[v + 1] - row_ptr[v]) - (orp[r + 1] - orp[r]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -806,29 +793,31 @@ tc_status tc_mid_prepare(tc_graph *g, hipStream_t s) {
     TC_TRY(tc_graph_alloc(g, &g->in_ptr, nn + 1, s));
     TC_TRY(tc_graph_alloc(g, &g->in_pair, m, s));
     tc_scratch tmp(s);
-    uint32_t *key = nullptr, *key2 = nullptr, *st = nullptr, *en = nullptr;
-    uint64_t *val = nullptr, *val2 = nullptr;
     int64_t *len = nullptr;
-    TC_TRY(tmp.get(&key, m));
-    TC_TRY(tmp.get(&key2, m));
-    TC_TRY(tmp.get(&val2, m));
-    TC_TRY(tmp.get(&st, nn));
-    TC_TRY(tmp.get(&en, nn));
     TC_TRY(tmp.get(&len, nn));
-    val = g->in_pair;
-    k_slot_keys<<<grid_for(m), BK, 0, s>>>(m, g->orow, g->ocol, key, val);
-    TC_LAUNCHED();
-    uint64_t *vres = val, *vswap = val2;
-    TC_TRY(tc_sort_u32_u64(&key, &vres, &key2, &vswap, m, g->bits, s));
-    if (vres != g->in_pair)
-        TC_HIP(hipMemcpyAsync(g->in_pair, vres, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
-    TC_HIP(hipMemsetAsync(st, 0, sizeof(uint32_t) * nn, s));
-    TC_HIP(hipMemsetAsync(en, 0, sizeof(uint32_t) * nn, s));
-    k_in_runs<<<grid_for(m), BK, 0, s>>>(key, m, st, en);
-    TC_LAUNCHED();
-    k_in_len<<<grid_for(n), BK, 0, s>>>(n, st, en, len);
-    TC_LAUNCHED();
-    TC_TRY(tc_scan_i64(len, g->in_ptr, n, g->in_ptr + n, s));
+    if (m > 0) {
+        // (row << 32 | slot) of every slot, in order of the pivot (stable:
+        // by row within a pivot)
+        uint32_t *key = nullptr, *key2 = nullptr;
+        uint64_t *val2 = nullptr;
+        TC_TRY(tmp.get(&key, m));
+        TC_TRY(tmp.get(&key2, m));
+        TC_TRY(tmp.get(&val2, m));
+        uint64_t *val = g->in_pair;
+        TC_TRY(tc_sort_u32_index_hi((const uint32_t *)g->ocol, (const uint32_t *)g->orow, &key, &val,
+                                    &key2, &val2, m, g->bits, s));
+        if (val != g->in_pair) {  // the result is in the scratch buffer: swap ownership
+            tmp.exchange(val, g->in_pair);
+            g->in_pair = val;
+        }
+    }
+    if (n > 0) {
+        k_in_len<<<grid_for(n), BK, 0, s>>>(n, g->perm, g->row_ptr, g->orp, len);
+        TC_LAUNCHED();
+        TC_TRY(tc_scan_i64(len, g->in_ptr, n, g->in_ptr + n, s));
+    } else {
+        TC_HIP(hipMemsetAsync(g->in_ptr, 0, sizeof(int64_t), s));
+    }
     return bit_rows_prepare(g, s);
 }
 

@@ -104,6 +104,10 @@ tc_status tc_sort_u32_from(const uint32_t *src, uint32_t **keys, uint32_t **tmp_
 tc_status tc_sort_u32_index(const uint32_t *src, uint32_t **keys, uint32_t **vals,
                             uint32_t **tmp_keys, uint32_t **tmp_vals, int64_t n, int bits,
                             hipStream_t s);
+// the same with 64-bit values (hi[i] << 32) | i
+tc_status tc_sort_u32_index_hi(const uint32_t *src, const uint32_t *hi, uint32_t **keys,
+                               uint64_t **vals, uint32_t **tmp_keys, uint64_t **tmp_vals,
+                               int64_t n, int bits, hipStream_t s);
 tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s);
 tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,

@@ -56,7 +56,7 @@ template <typename K, typename V, bool HAS_VAL>
 __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
     const K *__restrict__ kin, const V *__restrict__ vin, K *__restrict__ kout,
     V *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offsets,
-    int64_t tiles) {
+    int64_t tiles, const uint32_t *__restrict__ vhi) {
     // The tile is first put in digit order in LDS, then written out by
     // consecutive threads to consecutive positions of each digit's run, so
     // the global stores coalesce.
@@ -83,8 +83,21 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
         int64_t i = wbase + it * TC_WAVE + lane;
         bool valid = i < n;
         key[it] = valid ? kin[i] : (K)0;
-        // no value array: the value is the element's index
-        if constexpr (HAS_VAL) val[it] = valid ? (vin ? vin[i] : (V)i) : (V)0;
+        // no value array: the value is the element's index, with vhi[i] in
+        // the high half for 64-bit values when vhi is given
+        if constexpr (HAS_VAL) {
+            V v = 0;
+            if (valid) {
+                if (vin) {
+                    v = vin[i];
+                } else {
+                    v = (V)i;
+                    if constexpr (sizeof(V) == 8)
+                        if (vhi) v |= (V)vhi[i] << 32;
+                }
+            }
+            val[it] = v;
+        }
     }
 #pragma unroll
     for (int it = 0; it < SORT_ITEMS; ++it) {
@@ -158,7 +171,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
 // written to the buffers.
 template <typename K, typename V, bool HAS_VAL>
 tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bits, hipStream_t s,
-                     const K *src = nullptr, bool iota = false) {
+                     const K *src = nullptr, bool iota = false, const uint32_t *vhi = nullptr) {
     if (n < 0 || bits < 0 || bits > (int)(8 * sizeof(K))) return TC_ERR_INVALID_ARG;
     const bool fresh = src != nullptr || iota;
     if (n == 0 || (!fresh && (n <= 1 || bits == 0))) return TC_OK;
@@ -175,7 +188,8 @@ tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bi
         TC_LAUNCHED();
         TC_TRY(tc_scan_u32(counts, counts, tiles * RADIX, nullptr, s));
         k_radix_scatter<K, V, HAS_VAL><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(
-            in, vin, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift, counts, tiles);
+            in, vin, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift, counts, tiles,
+            shift == 0 ? vhi : nullptr);
         TC_LAUNCHED();
         K *tk = *keys;
         *keys = *tkeys;
@@ -207,6 +221,13 @@ tc_status tc_sort_u32_index(const uint32_t *src, uint32_t **keys, uint32_t **val
                             hipStream_t s) {
     return radix_sort<uint32_t, uint32_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s, src,
                                                 true);
+}
+
+tc_status tc_sort_u32_index_hi(const uint32_t *src, const uint32_t *hi, uint32_t **keys,
+                               uint64_t **vals, uint32_t **tmp_keys, uint64_t **tmp_vals,
+                               int64_t n, int bits, hipStream_t s) {
+    return radix_sort<uint32_t, uint64_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s, src,
+                                                true, hi);
 }
 
 tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
