@@ -210,39 +210,50 @@ __global__ void k_num_big(const int32_t *__restrict__ big, int64_t nbig,
 // transposition (available once the middle-pivot count has run): the
 // neighbours of rank row r are its out-slots k (N_H(r), ocol[k]) and its
 // in-pairs (u, k) (N_L(r)), and every edge's support sits at its oriented
-// slot, so the symmetric adjacency is not needed.  Rows (out + in entries)
-// longer than BIG_DEG go to a workgroup each.
+// slot, so the symmetric adjacency is not needed.  A row's entries are its
+// out-slots followed by its in-pairs.  Rows of up to RANK_SMALL entries go
+// to 16-lane groups; longer ones are cut into chunks of RANK_CHUNK entries,
+// one workgroup each, whose partial sums the row's first chunk adds up in a
+// second kernel (no atomics, and a hub no longer holds one workgroup for the
+// whole of its row).
 // ---------------------------------------------------------------------------
+constexpr int64_t RANK_SMALL = 256;
+constexpr int64_t RANK_CHUNK = 2048;
+
 __device__ __forceinline__ int64_t rank_row_len(const int64_t *__restrict__ orp,
                                                 const int64_t *__restrict__ in_ptr, int64_t r) {
     return (orp[r + 1] - orp[r]) + (in_ptr[r + 1] - in_ptr[r]);
 }
 
-// Σ over row r's edges of sup (PASS 1) or of tri(other end) weighted 1 if
-// the edge has support, 3 if not (PASS 2), over the lanes tid, tid + L, ...
-// PASS 1 also packs each in-pair as its lower end with bit 31 set when the
-// edge has no support (in_uw, in in_pair's order), so PASS 2 reads one
-// coalesced word per in-pair instead of gathering the support again.
+// Σ over entries [a, b) of row r of sup (PASS 1) or of tri(other end)
+// weighted 1 if the edge has support, 3 if not (PASS 2), over the lanes
+// tid, tid + L, ...  PASS 1 also packs each in-pair as its lower end with
+// bit 31 set when the edge has no support (in_uw, in in_pair's order), so
+// PASS 2 reads one coalesced word per in-pair instead of gathering the
+// support again.
 template <int PASS>
-__device__ __forceinline__ uint64_t rank_row_sum(int64_t r, int tid, int L,
-                                                 const int64_t *__restrict__ orp,
-                                                 const int32_t *__restrict__ ocol,
-                                                 const int64_t *__restrict__ in_ptr,
-                                                 const uint64_t *__restrict__ in_pair,
-                                                 const uint32_t *__restrict__ osup,
-                                                 uint32_t *__restrict__ in_uw,
-                                                 const uint64_t *__restrict__ tri_r) {
+__device__ __forceinline__ uint64_t rank_range_sum(int64_t r, int64_t a, int64_t b, int tid, int L,
+                                                   const int64_t *__restrict__ orp,
+                                                   const int32_t *__restrict__ ocol,
+                                                   const int64_t *__restrict__ in_ptr,
+                                                   const uint64_t *__restrict__ in_pair,
+                                                   const uint32_t *__restrict__ osup,
+                                                   uint32_t *__restrict__ in_uw,
+                                                   const uint64_t *__restrict__ tri_r) {
+    const int64_t ob = orp[r], olen = orp[r + 1] - ob, ib = in_ptr[r];
     uint64_t acc = 0;
-    for (int64_t k = orp[r] + tid; k < orp[r + 1]; k += L) {
+    for (int64_t t = a + tid; t < (b < olen ? b : olen); t += L) {
+        const int64_t k = ob + t;
         const uint32_t sp = osup[k];
         if constexpr (PASS == 1) {
             acc += sp;
         } else {
-            const uint64_t t = tri_r[ocol[k]];
-            acc += sp ? t : 3 * t;
+            const uint64_t x = tri_r[ocol[k]];
+            acc += sp ? x : 3 * x;
         }
     }
-    for (int64_t i = in_ptr[r] + tid; i < in_ptr[r + 1]; i += L) {
+    for (int64_t t = (a > olen ? a : olen) + tid; t < b; t += L) {
+        const int64_t i = ib + (t - olen);
         if constexpr (PASS == 1) {
             const uint64_t pr = in_pair[i];
             const uint32_t sp = osup[(uint32_t)pr];
@@ -250,8 +261,8 @@ __device__ __forceinline__ uint64_t rank_row_sum(int64_t r, int tid, int L,
             in_uw[i] = (uint32_t)(pr >> 32) | (sp ? 0u : 0x80000000u);
         } else {
             const uint32_t w = in_uw[i];
-            const uint64_t t = tri_r[w & 0x7FFFFFFFu];
-            acc += (w >> 31) ? 3 * t : t;
+            const uint64_t x = tri_r[w & 0x7FFFFFFFu];
+            acc += (w >> 31) ? 3 * x : x;
         }
     }
     return acc;
@@ -280,58 +291,89 @@ __device__ __forceinline__ void rank_row_finish(int64_t r, uint64_t acc,
     }
 }
 
+struct RankArgs {
+    const int64_t *orp;
+    const int32_t *ocol;
+    const int64_t *in_ptr;
+    const uint64_t *in_pair;
+    const uint32_t *osup;
+    uint32_t *in_uw;
+    const int32_t *perm;
+    uint64_t *tri_r;
+    uint64_t *tri;
+    const uint64_t *triG;
+    const int64_t *vtx_off;
+    int32_t G;
+    uint64_t *num;
+    double *tcv;
+    uint32_t *err;
+};
+
 template <int PASS>
-__global__ void k_rank_rows(int32_t n, const int64_t *__restrict__ orp,
-                            const int32_t *__restrict__ ocol, const int64_t *__restrict__ in_ptr,
-                            const uint64_t *__restrict__ in_pair, const uint32_t *__restrict__ osup,
-                            uint32_t *__restrict__ in_uw,
-                            const int32_t *__restrict__ perm, uint64_t *__restrict__ tri_r,
-                            uint64_t *__restrict__ tri, const uint64_t *__restrict__ triG,
-                            const int64_t *__restrict__ vtx_off, int32_t G,
-                            uint64_t *__restrict__ num, double *__restrict__ tcv,
-                            uint32_t *__restrict__ err) {
+__global__ void k_rank_rows(int32_t n, RankArgs q) {
     const int sub = threadIdx.x % GS;
     const int64_t groups = (int64_t)gridDim.x * (blockDim.x / GS);
     for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GS; r < n; r += groups) {
-        if (rank_row_len(orp, in_ptr, r) > BIG_DEG) continue;
-        uint64_t acc = rank_row_sum<PASS>(r, sub, GS, orp, ocol, in_ptr, in_pair, osup, in_uw, tri_r);
+        const int64_t len = rank_row_len(q.orp, q.in_ptr, r);
+        if (len > RANK_SMALL) continue;
+        uint64_t acc = rank_range_sum<PASS>(r, 0, len, sub, GS, q.orp, q.ocol, q.in_ptr, q.in_pair,
+                                            q.osup, q.in_uw, q.tri_r);
         acc = group_sum(acc);
         if (sub == 0)
-            rank_row_finish<PASS>(r, acc, perm, tri_r, tri, triG, vtx_off, G, num, tcv, err);
+            rank_row_finish<PASS>(r, acc, q.perm, q.tri_r, q.tri, q.triG, q.vtx_off, q.G, q.num,
+                                  q.tcv, q.err);
     }
 }
 
+// chunk[c] = (row << 32) | index of the chunk within its row
 template <int PASS>
-__global__ void k_rank_rows_big(const int32_t *__restrict__ big, int64_t nbig,
-                                const int64_t *__restrict__ orp, const int32_t *__restrict__ ocol,
-                                const int64_t *__restrict__ in_ptr,
-                                const uint64_t *__restrict__ in_pair,
-                                const uint32_t *__restrict__ osup, uint32_t *__restrict__ in_uw,
-                                const int32_t *__restrict__ perm,
-                                uint64_t *__restrict__ tri_r, uint64_t *__restrict__ tri,
-                                const uint64_t *__restrict__ triG,
-                                const int64_t *__restrict__ vtx_off, int32_t G,
-                                uint64_t *__restrict__ num, double *__restrict__ tcv,
-                                uint32_t *__restrict__ err) {
-    __shared__ uint64_t red[16];
-    for (int64_t i = blockIdx.x; i < nbig; i += gridDim.x) {
-        const int64_t r = big[i];
-        uint64_t acc = rank_row_sum<PASS>(r, threadIdx.x, blockDim.x, orp, ocol, in_ptr, in_pair,
-                                          osup, in_uw, tri_r);
+__global__ __launch_bounds__(256) void k_rank_chunks(const uint64_t *__restrict__ chunk,
+                                                     int64_t nchunk, RankArgs q,
+                                                     uint64_t *__restrict__ part) {
+    __shared__ uint64_t red[4];
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+        const uint64_t w = chunk[c];
+        const int64_t r = (int64_t)(w >> 32);
+        const int64_t a = (int64_t)(uint32_t)w * RANK_CHUNK;
+        const int64_t len = rank_row_len(q.orp, q.in_ptr, r);
+        const int64_t b = a + RANK_CHUNK < len ? a + RANK_CHUNK : len;
+        uint64_t acc = rank_range_sum<PASS>(r, a, b, threadIdx.x, blockDim.x, q.orp, q.ocol,
+                                            q.in_ptr, q.in_pair, q.osup, q.in_uw, q.tri_r);
         acc = block_sum(acc, red);
-        if (threadIdx.x == 0)
-            rank_row_finish<PASS>(r, acc, perm, tri_r, tri, triG, vtx_off, G, num, tcv, err);
+        if (threadIdx.x == 0) part[c] = acc;
     }
 }
 
-__global__ void k_rank_big_flags(int32_t n, const int64_t *__restrict__ orp,
-                                 const int64_t *__restrict__ in_ptr, uint32_t *__restrict__ f) {
-    GRID_STRIDE(r, n) f[r] = rank_row_len(orp, in_ptr, r) > BIG_DEG ? 1u : 0u;
+// The first chunk of each row adds the row's partial sums and finishes it.
+template <int PASS>
+__global__ void k_rank_chunks_finish(const uint64_t *__restrict__ chunk, int64_t nchunk,
+                                     const uint64_t *__restrict__ part, RankArgs q) {
+    GRID_STRIDE(c, nchunk) {
+        const uint64_t w = chunk[c];
+        if ((uint32_t)w != 0) continue;
+        const int64_t r = (int64_t)(w >> 32);
+        const int64_t nc = tc_div_up(rank_row_len(q.orp, q.in_ptr, r), RANK_CHUNK);
+        uint64_t acc = 0;
+        for (int64_t j = 0; j < nc; ++j) acc += part[c + j];
+        rank_row_finish<PASS>(r, acc, q.perm, q.tri_r, q.tri, q.triG, q.vtx_off, q.G, q.num, q.tcv,
+                              q.err);
+    }
 }
 
-__global__ void k_rank_big_write(int32_t n, const uint32_t *__restrict__ f,
-                                 const uint32_t *__restrict__ pos, int32_t *__restrict__ out) {
-    GRID_STRIDE(r, n) if (f[r]) out[pos[r]] = (int32_t)r;
+__global__ void k_rank_chunk_count(int32_t n, const int64_t *__restrict__ orp,
+                                   const int64_t *__restrict__ in_ptr, uint32_t *__restrict__ cnt) {
+    GRID_STRIDE(r, n) {
+        const int64_t len = rank_row_len(orp, in_ptr, r);
+        cnt[r] = len > RANK_SMALL ? (uint32_t)tc_div_up(len, RANK_CHUNK) : 0u;
+    }
+}
+
+__global__ void k_rank_chunk_write(int32_t n, const uint32_t *__restrict__ cnt,
+                                   const uint32_t *__restrict__ off, uint64_t *__restrict__ chunk) {
+    GRID_STRIDE(r, n) {
+        const uint32_t c = cnt[r];
+        for (uint32_t j = 0; j < c; ++j) chunk[off[r] + j] = ((uint64_t)r << 32) | j;
+    }
 }
 
 __global__ void k_big_flags(int32_t n, const int64_t *__restrict__ row_ptr, uint32_t *__restrict__ f) {
@@ -431,39 +473,41 @@ static tc_status aggregate_rank_space(tc_graph *g, hipStream_t s) {
         return TC_OK;
     }
     tc_scratch tmp(s);
-    uint32_t *f = nullptr, *pos = nullptr, *tot = nullptr;
-    int32_t *big = nullptr;
+    uint32_t *cnt = nullptr, *off = nullptr, *tot = nullptr, *in_uw = nullptr;
     uint64_t *tri_r = nullptr;
-    uint32_t *in_uw = nullptr;
     TC_TRY(tmp.get(&in_uw, m > 0 ? m : 1));
-    TC_TRY(tmp.get(&f, nn));
-    TC_TRY(tmp.get(&pos, nn));
+    TC_TRY(tmp.get(&cnt, nn));
+    TC_TRY(tmp.get(&off, nn));
     TC_TRY(tmp.get(&tot, 1));
-    TC_TRY(tmp.get(&big, nn));
     TC_TRY(tmp.get(&tri_r, nn));
-    k_rank_big_flags<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->in_ptr, f);
+    k_rank_chunk_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->in_ptr, cnt);
     TC_LAUNCHED();
-    TC_TRY(tc_scan_u32(f, pos, n, tot, s));
-    k_rank_big_write<<<grid_for(n), BK, 0, s>>>(n, f, pos, big);
-    TC_LAUNCHED();
+    TC_TRY(tc_scan_u32(cnt, off, n, tot, s));
     if (m > 0) {
         k_scatter_sup<<<grid_for(m), BK, 0, s>>>(m, g->o2e, g->osup, g->esup);
         TC_LAUNCHED();
     }
-    uint32_t hbig = 0;
-    TC_HIP(hipMemcpyAsync(&hbig, tot, 4, hipMemcpyDeviceToHost, s));
+    uint32_t hch = 0;
+    TC_HIP(hipMemcpyAsync(&hch, tot, 4, hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
-    const int64_t nbig = hbig;
+    const int64_t nchunk = hch;
+    uint64_t *chunk = nullptr, *part = nullptr;
+    TC_TRY(tmp.get(&chunk, nchunk > 0 ? nchunk : 1));
+    TC_TRY(tmp.get(&part, nchunk > 0 ? nchunk : 1));
+    if (nchunk > 0) {
+        k_rank_chunk_write<<<grid_for(n), BK, 0, s>>>(n, cnt, off, chunk);
+        TC_LAUNCHED();
+    }
+    RankArgs q{g->orp, g->ocol, g->in_ptr, g->in_pair, g->osup, in_uw, g->perm, tri_r,
+               g->tri, nullptr, voff, G, nullptr, nullptr, g->err};
     const unsigned small_grid = grid_for((int64_t)n * GS);
-    const unsigned big_grid = (unsigned)(nbig < 65536 ? (nbig > 0 ? nbig : 1) : 65536);
-    k_rank_rows<1><<<small_grid, BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, g->in_pair, g->osup,
-                                              in_uw, g->perm, tri_r, g->tri, nullptr, voff, G, nullptr,
-                                              nullptr, g->err);
+    const unsigned chunk_grid = (unsigned)(nchunk < 1048576 ? (nchunk > 0 ? nchunk : 1) : 1048576);
+    k_rank_rows<1><<<small_grid, BK, 0, s>>>(n, q);
     TC_LAUNCHED();
-    if (nbig > 0) {
-        k_rank_rows_big<1><<<big_grid, 1024, 0, s>>>(big, nbig, g->orp, g->ocol, g->in_ptr,
-                                                      g->in_pair, g->osup, in_uw, g->perm, tri_r, g->tri,
-                                                      nullptr, voff, G, nullptr, nullptr, g->err);
+    if (nchunk > 0) {
+        k_rank_chunks<1><<<chunk_grid, 256, 0, s>>>(chunk, nchunk, q, part);
+        TC_LAUNCHED();
+        k_rank_chunks_finish<1><<<grid_for(nchunk), BK, 0, s>>>(chunk, nchunk, part, q);
         TC_LAUNCHED();
     }
     k_tri_sum<<<grid_for(n, BK * 8), BK, 0, s>>>(n, g->tri, voff, G, (unsigned long long *)g->triG);
@@ -471,14 +515,15 @@ static tc_status aggregate_rank_space(tc_graph *g, hipStream_t s) {
     k_tri_finish<<<grid_for(G), BK, 0, s>>>(G, g->triG, g->err);
     TC_LAUNCHED();
     tc_prof_mark(g, 10, s);
-    k_rank_rows<2><<<small_grid, BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, g->in_pair, g->osup,
-                                              in_uw, g->perm, tri_r, g->tri, g->triG, voff, G, g->num,
-                                              g->tcv, g->err);
+    q.triG = g->triG;
+    q.num = g->num;
+    q.tcv = g->tcv;
+    k_rank_rows<2><<<small_grid, BK, 0, s>>>(n, q);
     TC_LAUNCHED();
-    if (nbig > 0) {
-        k_rank_rows_big<2><<<big_grid, 1024, 0, s>>>(big, nbig, g->orp, g->ocol, g->in_ptr,
-                                                      g->in_pair, g->osup, in_uw, g->perm, tri_r, g->tri,
-                                                      g->triG, voff, G, g->num, g->tcv, g->err);
+    if (nchunk > 0) {
+        k_rank_chunks<2><<<chunk_grid, 256, 0, s>>>(chunk, nchunk, q, part);
+        TC_LAUNCHED();
+        k_rank_chunks_finish<2><<<grid_for(nchunk), BK, 0, s>>>(chunk, nchunk, part, q);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 11, s);
