@@ -23,16 +23,25 @@ constexpr int RB = 8;
 constexpr int RADIX = 1 << RB;
 constexpr int SORT_BLOCK = 256;
 constexpr int SORT_WAVES = SORT_BLOCK / TC_WAVE;
-constexpr int SORT_ITEMS = 16;
-constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
+// Keys per thread: tiles of 8192 elements for elements (key and value) of
+// up to 8 bytes; bigger tiles mean longer runs per digit in the scatter's
+// stores.  Wider elements take tiles of 4096, since their registers would
+// otherwise leave one wavefront per SIMD, and are staged in two rounds
+// (keys, then values, through the same LDS buffer), which keeps their LDS
+// near 36 KB.
+template <typename K, typename V, bool HAS_VAL>
+constexpr int sort_items() {
+    return (sizeof(K) + (HAS_VAL ? sizeof(V) : 0)) <= 8 ? 32 : 16;
+}
 static_assert(SORT_BLOCK == RADIX, "one digit per thread in the scatter's digit scans");
 
 struct NoVal {};
 
-template <typename K>
+template <typename K, int SORT_ITEMS>
 __global__ __launch_bounds__(SORT_BLOCK) void k_radix_hist(const K *__restrict__ keys, int64_t n,
                                                            int shift, uint32_t *__restrict__ counts,
                                                            int64_t tiles) {
+    constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
     __shared__ uint32_t hist[SORT_WAVES][RADIX];
     for (int i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_BLOCK) (&hist[0][0])[i] = 0;
     __syncthreads();
@@ -52,19 +61,25 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_hist(const K *__restrict__
     }
 }
 
-template <typename K, typename V, bool HAS_VAL>
+template <typename K, typename V, bool HAS_VAL, int SORT_ITEMS>
 __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
     const K *__restrict__ kin, const V *__restrict__ vin, K *__restrict__ kout,
     V *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offsets,
     int64_t tiles, const uint32_t *__restrict__ vhi) {
+    constexpr int SORT_TILE = SORT_BLOCK * SORT_ITEMS;
     // The tile is first put in digit order in LDS, then written out by
     // consecutive threads to consecutive positions of each digit's run, so
     // the global stores coalesce.
     __shared__ uint32_t wcnt[SORT_WAVES][RADIX];
     __shared__ uint32_t gbase[RADIX];   // global start of the tile's keys of each digit
     __shared__ uint32_t lbase[RADIX];   // start of each digit within the tile
-    __shared__ K skey[SORT_TILE];
-    __shared__ V sval[HAS_VAL ? SORT_TILE : 1];
+    constexpr int KB = sizeof(K), VB = HAS_VAL ? sizeof(V) : 0;
+    constexpr bool SPLIT = HAS_VAL && KB + VB > 8;  // keys and values staged in turn
+    constexpr int STAGE = SORT_TILE * (SPLIT ? (KB > VB ? KB : VB) : KB + VB);
+    __shared__ __align__(16) unsigned char sraw[STAGE];
+    __shared__ uint8_t sdig[SPLIT ? SORT_TILE : 1];  // digit of each staged position
+    K *skey = reinterpret_cast<K *>(sraw);
+    V *sval = reinterpret_cast<V *>(SPLIT ? sraw : sraw + (size_t)SORT_TILE * KB);
     for (int i = threadIdx.x; i < SORT_WAVES * RADIX; i += SORT_BLOCK) (&wcnt[0][0])[i] = 0;
     __syncthreads();
 
@@ -144,14 +159,16 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
         lbase[threadIdx.x] = before;
     }
     __syncthreads();
+    // place of each item in the tile's digit order
 #pragma unroll
     for (int it = 0; it < SORT_ITEMS; ++it) {
         int64_t i = wbase + it * TC_WAVE + lane;
         if (i < n) {
             uint32_t d = (uint32_t)(key[it] >> shift) & (RADIX - 1);
-            uint32_t lp = lbase[d] + wcnt[w][d] + rnk[it];
-            skey[lp] = key[it];
-            if constexpr (HAS_VAL) sval[lp] = val[it];
+            rnk[it] += lbase[d] + wcnt[w][d];
+            skey[rnk[it]] = key[it];
+            if constexpr (SPLIT) sdig[rnk[it]] = (uint8_t)d;
+            else if constexpr (HAS_VAL) sval[rnk[it]] = val[it];
         }
     }
     __syncthreads();
@@ -160,7 +177,20 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
         const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
         const uint32_t pos = gbase[d] + (uint32_t)j - lbase[d];
         kout[pos] = k;
-        if constexpr (HAS_VAL) vout[pos] = sval[j];
+        if constexpr (HAS_VAL && !SPLIT) vout[pos] = sval[j];
+    }
+    if constexpr (SPLIT) {
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < SORT_ITEMS; ++it) {
+            int64_t i = wbase + it * TC_WAVE + lane;
+            if (i < n) sval[rnk[it]] = val[it];
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < tn; j += SORT_BLOCK) {
+            const uint32_t d = sdig[j];
+            vout[gbase[d] + (uint32_t)j - lbase[d]] = sval[j];
+        }
     }
 }
 
@@ -177,17 +207,18 @@ tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bi
     if (n == 0 || (!fresh && (n <= 1 || bits == 0))) return TC_OK;
     if (fresh && bits == 0) bits = 1;  // keys below 2^0 are all zero: one pass keeps the order
     if (n >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
-    int64_t tiles = tc_div_up(n, SORT_TILE);
+    constexpr int ITEMS = sort_items<K, V, HAS_VAL>();
+    int64_t tiles = tc_div_up(n, (int64_t)SORT_BLOCK * ITEMS);
     tc_scratch tmp(s);
     uint32_t *counts = nullptr;
     TC_TRY(tmp.get(&counts, tiles * RADIX));
     for (int shift = 0; shift < bits; shift += RB) {
         const K *in = (src && shift == 0) ? src : *keys;
         const V *vin = (HAS_VAL && !(iota && shift == 0)) ? *vals : nullptr;
-        k_radix_hist<K><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(in, n, shift, counts, tiles);
+        k_radix_hist<K, ITEMS><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(in, n, shift, counts, tiles);
         TC_LAUNCHED();
         TC_TRY(tc_scan_u32(counts, counts, tiles * RADIX, nullptr, s));
-        k_radix_scatter<K, V, HAS_VAL><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(
+        k_radix_scatter<K, V, HAS_VAL, ITEMS><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(
             in, vin, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift, counts, tiles,
             shift == 0 ? vhi : nullptr);
         TC_LAUNCHED();
