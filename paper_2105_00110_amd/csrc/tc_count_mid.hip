@@ -52,6 +52,17 @@ __host__ __device__ __forceinline__ int64_t bit_words(int64_t d) {
     return 32 * (q * (q + 1) / 2) + (q + 1) * r;
 }
 
+// bit_words in the index type I of the fold: 32-bit for rows below
+// FOLD_I32_MAX entries (every offset inside such a B_u fits), 64-bit
+// otherwise.
+template <typename I>
+__device__ __forceinline__ I bit_words_t(I x) {
+    if (x < 2) return 0;
+    const I q = (x - 1) >> 5, r = (x - 1) & 31;
+    return 32 * (q * (q + 1) / 2) + (q + 1) * r;
+}
+constexpr int64_t FOLD_I32_MAX = 32768;
+
 static inline unsigned grid_for(int64_t n, int block = BK) {
     int64_t g = tc_div_up(n, block);
     if (g < 1) g = 1;
@@ -457,41 +468,41 @@ __global__ __launch_bounds__(256) void k_fold(const int32_t *__restrict__ rows, 
     for (int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL; gi < nrows; gi += groups) {
         const int32_t r = rows[gi];
         const int64_t rs = orp[r];
-        const int64_t d = orp[r + 1] - rs;  // 2 <= d <= 64
-        const int64_t base = rowbase[r];
-        const int64_t sd = bit_words(d);
-        for (int64_t i = sub; i < d; i += GL) {
+        const int d = (int)(orp[r + 1] - rs);  // 2 <= d <= 64
+        const uint32_t *rb = bits + rowbase[r];  // B_u; offsets inside it fit 32 bits
+        const int sd = bit_words_t<int>(d);
+        for (int i = sub; i < d; i += GL) {
             uint32_t c = 0;
             if (i < d - 1) {
-                const int64_t off = base + sd - bit_words(d - i);
-                const int64_t nw = (d - 1 - i + 31) >> 5;
-                for (int64_t q = 0; q < nw; ++q) c += __popc(bits[off + q]);
+                const int off = sd - bit_words_t<int>(d - i);
+                const int nw = (d - 1 - i + 31) >> 5;
+                for (int q = 0; q < nw; ++q) c += __popc(rb[off + q]);
             }
             acc[i] = c;
         }
-        const int64_t nst = (d + 31) >> 5;
-        const int64_t G = nst >= GL ? 1 : GL / nst;
-        for (int64_t unit = sub; unit < nst * G; unit += GL) {
-            const int64_t c = unit % nst, g = unit / nst;
+        const int nst = (d + 31) >> 5;
+        const int G = nst >= GL ? 1 : GL / nst;
+        for (int unit = sub; unit < nst * G; unit += GL) {
+            const int c = unit % nst, g = unit / nst;
             uint32_t cnt[32];
 #pragma unroll
             for (int b = 0; b < 32; ++b) cnt[b] = 0;
             uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
             int fill = 0;
-            const int64_t imax = min(d - 2, 32 * c + 30);
-            for (int64_t i = g; i <= imax; i += G) {
-                const int64_t off = base + sd - bit_words(d - i);
-                const int64_t nw = (d - 1 - i + 31) >> 5;
-                const int64_t o = 32 * c - (i + 1);  // row-i bit of the stripe's first column
+            const int imax = min(d - 2, 32 * c + 30);
+            for (int i = g; i <= imax; i += G) {
+                const int off = sd - bit_words_t<int>(d - i);
+                const int nw = (d - 1 - i + 31) >> 5;
+                const int o = 32 * c - (i + 1);  // row-i bit of the stripe's first column
                 uint32_t w;
                 if (o >= 0) {
-                    const int64_t q = o >> 5;
-                    const int sh = (int)(o & 31);
-                    const uint32_t lo = q < nw ? bits[off + q] : 0u;
-                    const uint32_t hi = q + 1 < nw ? bits[off + q + 1] : 0u;
+                    const int q = o >> 5;
+                    const int sh = o & 31;
+                    const uint32_t lo = q < nw ? rb[off + q] : 0u;
+                    const uint32_t hi = q + 1 < nw ? rb[off + q + 1] : 0u;
                     w = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
                 } else {
-                    w = nw > 0 ? bits[off] << (int)(-o) : 0u;
+                    w = nw > 0 ? rb[off] << (-o) : 0u;
                 }
                 uint32_t carry = w;
 #pragma unroll
@@ -508,21 +519,29 @@ __global__ __launch_bounds__(256) void k_fold(const int32_t *__restrict__ rows, 
             planes_flush(pl, cnt);
 #pragma unroll
             for (int b = 0; b < 32; ++b) {
-                const int64_t j = 32 * c + b;
+                const int j = 32 * c + b;
                 if (j < d && cnt[b]) atomicAdd(&acc[j], cnt[b]);
             }
         }
-        for (int64_t j = sub; j < d; j += GL) {
+        for (int j = sub; j < d; j += GL) {
             const uint32_t v = acc[j];
             if (v) osup[rs + j] += v;  // the group owns row u's slots here
         }
     }
 }
 
+// Carry-save add of three bit vectors: s = a ^ b ^ c, cy = majority(a, b, c).
+__device__ __forceinline__ void csa(uint32_t a, uint32_t b, uint32_t c, uint32_t &s,
+                                    uint32_t &cy) {
+    const uint32_t u = a ^ b;
+    s = u ^ c;
+    cy = (a & b) | (u & c);
+}
+
 // The 32 bits of row i of B_u at the columns of stripe c (row i's bit b
 // is column i + 1 + b; bits outside the row read as 0).  lo/hi are the two
 // row words the stripe can touch, already loaded.
-__device__ __forceinline__ uint32_t stripe_bits(int64_t o, uint32_t lo, uint32_t hi) {
+__device__ __forceinline__ uint32_t stripe_bits(int o, uint32_t lo, uint32_t hi) {
     if (o < 0) return lo << (int)(-o);
     const int sh = (int)(o & 31);
     return sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
@@ -540,13 +559,119 @@ __device__ __forceinline__ uint32_t stripe_bits(int64_t o, uint32_t lo, uint32_t
 // longer than the LDS counters add to device memory with atomics instead.
 constexpr int FOLD_RC = 63;  // rows per flush: 6 counter planes hold up to 63
 
+// One row u of the big-row fold; rb = B_u's first word, sup = u's supports.
+template <typename I>
+__device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I d, bool in_lds,
+                                             uint32_t *__restrict__ colc,
+                                             uint32_t *__restrict__ sup) {
+    const int lane = __lane_id();
+    const I sd = bit_words_t<I>(d);
+    // row sums (the last slot has no row: it starts at 0)
+    for (I i = lane; i < d; i += TC_WAVE) {
+        uint32_t c = 0;
+        if (i < d - 1) {
+            const I off = sd - bit_words_t<I>(d - i);
+            const I nw = (d - 1 - i + 31) >> 5;
+            for (I q0 = 0; q0 < nw; q0 += 8) {
+                uint32_t x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = q0 + e < nw ? rb[off + q0 + e] : 0u;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) c += __popc(x[e]);
+            }
+        }
+        if (in_lds) colc[i] = c;
+        else if (c) atomicAdd(&sup[i], c);
+    }
+    // column sums: lane (stripe c, row group g) of a group of up to 64
+    // stripes; with fewer stripes than lanes the rows are dealt to
+    // G = 64 / stripes groups (row i to group i mod G), and the lanes of
+    // one group read consecutive words of one row at every step
+    const I nst = (d + 31) >> 5;
+    for (I sg = 0; sg < nst; sg += TC_WAVE) {
+        const I ns = min((I)TC_WAVE, nst - sg);
+        const I G = TC_WAVE / ns;
+        const I c = sg + lane % ns;
+        const I g = lane / ns;
+        const bool active = g < G;
+        // rows that reach some stripe of the group: i + 1 <= 32 (sg + ns - 1) + 31
+        const I ilast = min(d - 2, 32 * (sg + ns) - 2);
+        const I steps = (ilast + G) / G;  // rows per group, rounded up
+        uint32_t cnt[32];
+#pragma unroll
+        for (int b = 0; b < 32; ++b) cnt[b] = 0;
+        uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
+        int fill = 0;
+        for (I tb = 0; tb < steps; tb += 8) {
+            uint32_t lo[8], hi[8];
+            I oo[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const I i = g + G * (tb + e);
+                const I o = 32 * c - (i + 1);  // row bit of the stripe's column 0
+                lo[e] = 0u;
+                hi[e] = 0u;
+                oo[e] = -32;
+                if (active && i <= ilast && o > -32) {
+                    const I off = sd - bit_words_t<I>(d - i);
+                    const I nw = (d - 1 - i + 31) >> 5;
+                    const I q = o < 0 ? 0 : (o >> 5);
+                    oo[e] = o;
+                    if (q < nw) lo[e] = rb[off + q];
+                    if (o >= 0 && q + 1 < nw) hi[e] = rb[off + q + 1];
+                }
+            }
+            uint32_t w[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) w[e] = oo[e] > -32 ? stripe_bits((int)oo[e], lo[e], hi[e]) : 0u;
+            // the 8 rows into the planes by a carry-save tree: pl[0..2] are
+            // the ones, twos and fours of every column, and the one eights
+            // word of the step ripples into pl[3..5]
+            uint32_t t2a, t2b, t4a, t4b, e8;
+            csa(pl[0], w[0], w[1], pl[0], t2a);
+            csa(pl[0], w[2], w[3], pl[0], t2b);
+            csa(pl[1], t2a, t2b, pl[1], t4a);
+            csa(pl[0], w[4], w[5], pl[0], t2a);
+            csa(pl[0], w[6], w[7], pl[0], t2b);
+            csa(pl[1], t2a, t2b, pl[1], t4b);
+            csa(pl[2], t4a, t4b, pl[2], e8);
+#pragma unroll
+            for (int k = 3; k < 6; ++k) {
+                const uint32_t tk = pl[k] & e8;
+                pl[k] ^= e8;
+                e8 = tk;
+            }
+            fill += 8;
+            if (fill > FOLD_RC - 8) {
+                planes_flush(pl, cnt);
+                fill = 0;
+            }
+        }
+        planes_flush(pl, cnt);
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < 32; ++b) {
+                const I j = 32 * c + b;
+                if (j < d && cnt[b]) {
+                    if (in_lds) atomicAdd(&colc[j], cnt[b]);
+                    else atomicAdd(&sup[j], cnt[b]);
+                }
+            }
+        }
+    }
+    if (in_lds)
+        for (I j = lane; j < d; j += TC_WAVE) {
+            const uint32_t v = colc[j];
+            if (v) sup[j] += v;  // the wavefront owns row u's slots here
+        }
+}
+
 __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ rows, int64_t nrows,
                                                   const int64_t *__restrict__ orp,
                                                   const int64_t *__restrict__ rowbase,
                                                   const uint32_t *__restrict__ bits,
                                                   uint32_t *__restrict__ osup, int dcap) {
     extern __shared__ uint32_t colc_all[];
-    const int lane = __lane_id();
     const int wv = threadIdx.x / TC_WAVE;
     uint32_t *colc = colc_all + (size_t)wv * dcap;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / TC_WAVE);
@@ -556,97 +681,12 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
         const int32_t r = rows[nrows - 1 - gi];
         const int64_t rs = orp[r];
         const int64_t d = orp[r + 1] - rs;
-        const int64_t base = rowbase[r];
-        const int64_t sd = bit_words(d);
+        const uint32_t *rb = bits + rowbase[r];
         const bool in_lds = d <= dcap;
-        // row sums (the last slot has no row: it starts at 0)
-        for (int64_t i = lane; i < d; i += TC_WAVE) {
-            uint32_t c = 0;
-            if (i < d - 1) {
-                const int64_t off = base + sd - bit_words(d - i);
-                const int64_t nw = (d - 1 - i + 31) >> 5;
-                for (int64_t q0 = 0; q0 < nw; q0 += 8) {
-                    uint32_t x[8];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) x[e] = q0 + e < nw ? bits[off + q0 + e] : 0u;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) c += __popc(x[e]);
-                }
-            }
-            if (in_lds) colc[i] = c;
-            else if (c) atomicAdd(&osup[rs + i], c);
-        }
-        // column sums: lane (stripe c, row group g) of a group of up to 64
-        // stripes; with fewer stripes than lanes the rows are dealt to
-        // G = 64 / stripes groups (row i to group i mod G), and the lanes of
-        // one group read consecutive words of one row at every step
-        const int64_t nst = (d + 31) >> 5;
-        for (int64_t sg = 0; sg < nst; sg += TC_WAVE) {
-            const int64_t ns = min((int64_t)TC_WAVE, nst - sg);
-            const int64_t G = TC_WAVE / ns;
-            const int64_t c = sg + lane % ns;
-            const int64_t g = lane / ns;
-            const bool active = g < G;
-            // rows that reach some stripe of the group: i + 1 <= 32 (sg + ns - 1) + 31
-            const int64_t ilast = min(d - 2, 32 * (sg + ns) - 2);
-            const int64_t steps = (ilast + G) / G;  // rows per group, rounded up
-            uint32_t cnt[32];
-#pragma unroll
-            for (int b = 0; b < 32; ++b) cnt[b] = 0;
-            uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
-            int fill = 0;
-            for (int64_t tb = 0; tb < steps; tb += 8) {
-                uint32_t lo[8], hi[8];
-                int64_t oo[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int64_t i = g + G * (tb + e);
-                    const int64_t o = 32 * c - (i + 1);  // row bit of the stripe's column 0
-                    lo[e] = 0u;
-                    hi[e] = 0u;
-                    oo[e] = -32;
-                    if (active && i <= ilast && o > -32) {
-                        const int64_t off = base + sd - bit_words(d - i);
-                        const int64_t nw = (d - 1 - i + 31) >> 5;
-                        const int64_t q = o < 0 ? 0 : (o >> 5);
-                        oo[e] = o;
-                        if (q < nw) lo[e] = bits[off + q];
-                        if (o >= 0 && q + 1 < nw) hi[e] = bits[off + q + 1];
-                    }
-                }
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    uint32_t carry = oo[e] > -32 ? stripe_bits(oo[e], lo[e], hi[e]) : 0u;
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) {
-                        const uint32_t tk = pl[k] & carry;
-                        pl[k] ^= carry;
-                        carry = tk;
-                    }
-                }
-                fill += 8;
-                if (fill > FOLD_RC - 8) {
-                    planes_flush(pl, cnt);
-                    fill = 0;
-                }
-            }
-            planes_flush(pl, cnt);
-            if (active) {
-#pragma unroll
-                for (int b = 0; b < 32; ++b) {
-                    const int64_t j = 32 * c + b;
-                    if (j < d && cnt[b]) {
-                        if (in_lds) atomicAdd(&colc[j], cnt[b]);
-                        else atomicAdd(&osup[rs + j], cnt[b]);
-                    }
-                }
-            }
-        }
-        if (in_lds)
-            for (int64_t j = lane; j < d; j += TC_WAVE) {
-                const uint32_t v = colc[j];
-                if (v) osup[rs + j] += v;  // the wavefront owns row u's slots here
-            }
+        if (d < FOLD_I32_MAX)
+            fold_big_row<int32_t>(rb, (int32_t)d, in_lds, colc, osup + rs);
+        else
+            fold_big_row<int64_t>(rb, d, in_lds, colc, osup + rs);
     }
 }
 
