@@ -331,59 +331,74 @@ __global__ void k_dplus_by_rank(int32_t n, const uint32_t *__restrict__ cursor,
     if (__lane_id() == 0 && mx) atomicMax(dmax, mx);
 }
 
-// Buckets of lo < d <= GL entries (GL <= SEG_WAVE), GL lanes each: every
-// wavefront reads the sizes of 64 consecutive vertices, takes those of its
-// class from the ballot, 64 / GL at a time, and each lane places its entry by
-// the number of smaller keys in its group (keys of a bucket are distinct
-// ranks).  The grid strides over the vertices, so there is no wavefront per
-// vertex to dispatch.
+// Buckets of 1..SEG_WAVE entries.  Every wavefront reads the sizes of 64
+// consecutive vertices and sorts their buckets by size class (lo, GL],
+// GL = 8, 16, 32, 64: GL lanes per bucket, 64 / GL buckets at a time, taken
+// from the ballot of the class.  Each lane places its entry by the number of
+// smaller keys in its group (keys of a bucket are distinct ranks).  The grid
+// strides over the vertices, so there is no wavefront per vertex to
+// dispatch.
 template <int GL>
-__global__ __launch_bounds__(256) void k_orient_small(
-    int32_t n, uint32_t lo, const int64_t *__restrict__ row_ptr,
-    const uint32_t *__restrict__ cursor, const int32_t *__restrict__ rank,
-    const int64_t *__restrict__ orp, const uint64_t *__restrict__ tbuf,
-    int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e, int32_t *__restrict__ orow) {
+__device__ __forceinline__ void orient_class(int64_t x0, uint32_t dl, uint32_t lo, uint32_t *wsk,
+                                             const int64_t *__restrict__ row_ptr,
+                                             const int32_t *__restrict__ rank,
+                                             const int64_t *__restrict__ orp,
+                                             const uint64_t *__restrict__ tbuf,
+                                             int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
+                                             int32_t *__restrict__ orow) {
     static_assert(GL <= SEG_WAVE && TC_WAVE % GL == 0, "group size");
     constexpr int GPW = TC_WAVE / GL;
+    const int lane = __lane_id();
+    const int grp = lane / GL, sl = lane % GL;
+    uint32_t *gsk = wsk + grp * GL;
+    uint64_t mask = __ballot(dl > lo && dl <= (uint32_t)GL);
+    while (mask) {
+        // this group's vertex: the grp-th set bit of the mask, if any
+        uint64_t mm = mask;
+        for (int q = 0; q < grp && mm; ++q) mm &= mm - 1;
+        const bool has = mm != 0;
+        const int j = has ? __ffsll((long long)mm) - 1 : 0;
+        for (int q = 0; q < GPW && mask; ++q) mask &= mask - 1;
+        const int d = (int)__shfl(dl, j, TC_WAVE);
+        const int64_t x = x0 + j;
+        const bool mine = has && sl < d;
+        uint32_t key = 0xFFFFFFFFu, val = 0;
+        if (mine) {
+            const uint64_t w = tbuf[row_ptr[x] + sl];
+            key = (uint32_t)(w >> 32);
+            val = (uint32_t)w;
+        }
+        gsk[sl] = key;
+        __builtin_amdgcn_wave_barrier();
+        if (mine) {
+            int pos = 0;
+            for (int t = 0; t < d; ++t) pos += gsk[t] < key ? 1 : 0;
+            const int32_t rx = rank[x];
+            const int64_t k = orp[rx] + pos;
+            ocol[k] = (int32_t)key;
+            o2e[k] = val;
+            orow[k] = rx;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_orient_small(
+    int32_t n, const int64_t *__restrict__ row_ptr, const uint32_t *__restrict__ cursor,
+    const int32_t *__restrict__ rank, const int64_t *__restrict__ orp,
+    const uint64_t *__restrict__ tbuf, int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
+    int32_t *__restrict__ orow) {
     __shared__ uint32_t sk[4][TC_WAVE];
     const int wv = threadIdx.x / TC_WAVE;
     const int lane = __lane_id();
-    const int grp = lane / GL, sl = lane % GL;
-    uint32_t *gsk = &sk[wv][grp * GL];
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     for (int64_t x0 = ((int64_t)blockIdx.x * 4 + wv) * TC_WAVE; x0 < n; x0 += nwaves * TC_WAVE) {
         const int64_t xl = x0 + lane;
         const uint32_t dl = xl < n ? cursor[xl] : 0u;
-        uint64_t mask = __ballot(dl > lo && dl <= (uint32_t)GL);
-        while (mask) {
-            // this group's vertex: the grp-th set bit of the mask, if any
-            uint64_t mm = mask;
-            for (int q = 0; q < grp && mm; ++q) mm &= mm - 1;
-            const bool has = mm != 0;
-            const int j = has ? __ffsll((long long)mm) - 1 : 0;
-            for (int q = 0; q < GPW && mask; ++q) mask &= mask - 1;
-            const int d = (int)__shfl(dl, j, TC_WAVE);
-            const int64_t x = x0 + j;
-            const bool mine = has && sl < d;
-            uint32_t key = 0xFFFFFFFFu, val = 0;
-            if (mine) {
-                const uint64_t w = tbuf[row_ptr[x] + sl];
-                key = (uint32_t)(w >> 32);
-                val = (uint32_t)w;
-            }
-            gsk[sl] = key;
-            __builtin_amdgcn_wave_barrier();
-            if (mine) {
-                int pos = 0;
-                for (int t = 0; t < d; ++t) pos += gsk[t] < key ? 1 : 0;
-                const int32_t rx = rank[x];
-                const int64_t k = orp[rx] + pos;
-                ocol[k] = (int32_t)key;
-                o2e[k] = val;
-                orow[k] = rx;
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
+        orient_class<8>(x0, dl, 0, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
+        orient_class<16>(x0, dl, 8, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
+        orient_class<32>(x0, dl, 16, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
+        orient_class<64>(x0, dl, 32, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
     }
 }
 
@@ -509,22 +524,16 @@ static tc_status compact_vertices(int32_t n, uint32_t *f, int32_t *out, uint32_t
     return TC_OK;
 }
 
-static tc_status orient_impl(tc_graph *g, hipStream_t s);
-
-tc_status tc_orient(tc_graph *g, hipStream_t s) {
-    const tc_status st = orient_impl(g, s);
-    // the order by larger id served the placement only
-    if (g->lt_key) {
-        tc_dev_free(g->lt_key, s);
-        tc_dev_free(g->lt_val, s);
-        g->lt_key = nullptr;
-        g->lt_val = nullptr;
-        g->bytes -= 2 * sizeof(uint32_t) * (size_t)(g->m > 0 ? g->m : 1);
-    }
-    return st;
+void tc_release_transposition(tc_graph *g, hipStream_t s) {
+    if (!g->lt_key) return;
+    tc_dev_free(g->lt_key, s);
+    tc_dev_free(g->lt_val, s);
+    g->lt_key = nullptr;
+    g->lt_val = nullptr;
+    g->bytes -= 2 * sizeof(uint32_t) * (size_t)g->m;
 }
 
-static tc_status orient_impl(tc_graph *g, hipStream_t s) {
+tc_status tc_orient(tc_graph *g, hipStream_t s) {
     const int32_t n = g->n;
     const int64_t m = g->m;
     int64_t nn = n > 0 ? n : 1;
@@ -600,17 +609,8 @@ static tc_status orient_impl(tc_graph *g, hipStream_t s) {
     {
         const int64_t want = tc_div_up(n, 4 * TC_WAVE);
         const unsigned grid = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
-        k_orient_small<8><<<grid, BK, 0, s>>>(n, 0, g->row_ptr, cursor, g->rank, g->orp, tbuf,
-                                              g->ocol, g->o2e, g->orow);
-        TC_LAUNCHED();
-        k_orient_small<16><<<grid, BK, 0, s>>>(n, 8, g->row_ptr, cursor, g->rank, g->orp, tbuf,
-                                               g->ocol, g->o2e, g->orow);
-        TC_LAUNCHED();
-        k_orient_small<32><<<grid, BK, 0, s>>>(n, 16, g->row_ptr, cursor, g->rank, g->orp, tbuf,
-                                               g->ocol, g->o2e, g->orow);
-        TC_LAUNCHED();
-        k_orient_small<64><<<grid, BK, 0, s>>>(n, 32, g->row_ptr, cursor, g->rank, g->orp, tbuf,
-                                               g->ocol, g->o2e, g->orow);
+        k_orient_small<<<grid, BK, 0, s>>>(n, g->row_ptr, cursor, g->rank, g->orp, tbuf, g->ocol,
+                                           g->o2e, g->orow);
         TC_LAUNCHED();
     }
     if (nmid > 0) {
@@ -656,13 +656,11 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
         uint64_t *keys = nullptr, *keys2 = nullptr;
         TC_TRY(tmp.get(&keys, P));
         TC_TRY(tmp.get(&keys2, P));
+        // an id out of range makes a sentinel key (dropped like a self
+        // loop) and sets err, which is read back with the edge count
         k_make_keys<<<grid_for(P), BK, 0, s>>>(d_src, d_dst, P, n, bits, d_pair_off, d_vtx_off,
                                                num_graphs, keys, g->err);
         TC_LAUNCHED();
-        uint32_t h_err = 0;
-        TC_HIP(hipMemcpyAsync(&h_err, g->err, 4, hipMemcpyDeviceToHost, s));
-        TC_HIP(hipStreamSynchronize(s));
-        if (h_err) return TC_ERR_VERTEX_RANGE;
         TC_TRY(tc_sort_u64(&keys, &keys2, P, 2 * bits, s));
         uint32_t *pos = nullptr, *d_m = nullptr;
         TC_TRY(tmp.get(&pos, P));
@@ -670,9 +668,11 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
         k_unique_flags<<<grid_for(P), BK, 0, s>>>(keys, P, sentinel, pos);
         TC_LAUNCHED();
         TC_TRY(tc_scan_u32(pos, pos, P, d_m, s));
-        uint32_t h_m = 0;
+        uint32_t h_m = 0, h_err = 0;
+        TC_HIP(hipMemcpyAsync(&h_err, g->err, 4, hipMemcpyDeviceToHost, s));
         TC_HIP(hipMemcpyAsync(&h_m, d_m, 4, hipMemcpyDeviceToHost, s));
         TC_HIP(hipStreamSynchronize(s));
+        if (h_err) return TC_ERR_VERTEX_RANGE;
         m = h_m;
         TC_TRY(tc_graph_alloc(g, &g->eu, m, s));
         TC_TRY(tc_graph_alloc(g, &g->ev, m, s));
@@ -798,23 +798,25 @@ tc_status tc_ensure_symmetric(tc_graph *g, hipStream_t s) {
     TC_TRY(tc_graph_alloc(g, &g->col, 2 * m, s));
     TC_TRY(tc_graph_alloc(g, &g->sym2e, 2 * m, s));
     if (m == 0) return TC_OK;
-    // the transposition: canonical edges sorted by their larger end, and
-    // the run of every vertex in that order
+    // the transposition: canonical edges sorted by their larger end (kept
+    // from the build unless the middle-pivot count released it), and the
+    // run of every vertex in that order
     tc_scratch tmp(s);
-    uint32_t *tkey = nullptr, *tval = nullptr, *tkey2 = nullptr, *tval2 = nullptr;
+    uint32_t *tkey = g->lt_key, *tval = g->lt_val;
     uint32_t *ls = nullptr, *le = nullptr;
-    TC_TRY(tmp.get(&tkey, m));
-    TC_TRY(tmp.get(&tval, m));
-    TC_TRY(tmp.get(&tkey2, m));
-    TC_TRY(tmp.get(&tval2, m));
+    if (!tkey) {
+        uint32_t *tkey2 = nullptr, *tval2 = nullptr;
+        TC_TRY(tmp.get(&tkey, m));
+        TC_TRY(tmp.get(&tval, m));
+        TC_TRY(tmp.get(&tkey2, m));
+        TC_TRY(tmp.get(&tval2, m));
+        TC_TRY(tc_sort_u32_index((const uint32_t *)g->ev, &tkey, &tval, &tkey2, &tval2, m, g->bits,
+                                 s));
+    }
     TC_TRY(tmp.get(&ls, nn));
     TC_TRY(tmp.get(&le, nn));
     TC_HIP(hipMemsetAsync(ls, 0, sizeof(uint32_t) * nn, s));
     TC_HIP(hipMemsetAsync(le, 0, sizeof(uint32_t) * nn, s));
-    TC_HIP(hipMemcpyAsync(tkey, g->ev, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
-    k_iota<<<grid_for(m), BK, 0, s>>>(tval, m);
-    TC_LAUNCHED();
-    TC_TRY(tc_sort_u32_u32(&tkey, &tval, &tkey2, &tval2, m, g->bits, s));
     k_runs<<<grid_for(m), BK, 0, s>>>(GetU32{tkey}, m, ls, le);
     TC_LAUNCHED();
     k_fill_lower<<<grid_for(m), BK, 0, s>>>(m, tkey, tval, ls, g->row_ptr, g->eu, g->col, g->sym2e);
@@ -822,5 +824,6 @@ tc_status tc_ensure_symmetric(tc_graph *g, hipStream_t s) {
     k_fill_upper<<<grid_for(m), BK, 0, s>>>(m, g->eu, g->ev, g->run_us, ls, le, g->row_ptr, g->col,
                                             g->sym2e);
     TC_LAUNCHED();
+    tc_release_transposition(g, s);
     return TC_OK;
 }

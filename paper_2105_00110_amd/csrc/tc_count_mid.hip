@@ -826,6 +826,9 @@ tc_status plan_write(const tc_graph *g, ItemPlan &p, tc_scratch &keep, hipStream
 static tc_status bit_rows_prepare(tc_graph *g, hipStream_t s);
 
 tc_status tc_mid_prepare(tc_graph *g, hipStream_t s) {
+    // the order by larger id is not needed from here on (the symmetric
+    // fill sorts again if it is ever asked for)
+    tc_release_transposition(g, s);
     if (g->in_pair) return bit_rows_prepare(g, s);
     const int32_t n = g->n;
     const int64_t m = g->m;

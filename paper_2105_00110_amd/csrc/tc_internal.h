@@ -137,8 +137,9 @@ struct tc_graph {
     // kept from the build so that col / sym2e can be filled on demand: the
     // first canonical edge whose smaller end is v
     uint32_t *run_us = nullptr;                     // [n]
-    // from the build to the orientation only: the canonical edges ordered by
-    // their larger end (key = ev, val = edge)
+    // the canonical edges ordered by their larger end (key = ev, val =
+    // edge): from the build to the orientation, and on to the symmetric
+    // fill unless the middle-pivot count releases them first
     uint32_t *lt_key = nullptr, *lt_val = nullptr;  // [m]
     // degree order: perm[r] = vertex of rank r, rank[v]
     int32_t *rank = nullptr, *perm = nullptr;       // [n]
@@ -199,6 +200,8 @@ tc_status tc_aggregate(tc_graph *g, hipStream_t s);
 // Fills the symmetric adjacency col / sym2e from what the build kept
 // (once per handle; no-op when filled).  tc_build.hip.
 tc_status tc_ensure_symmetric(tc_graph *g, hipStream_t s);
+// Frees lt_key / lt_val (no-op when gone).  tc_build.hip.
+void tc_release_transposition(tc_graph *g, hipStream_t s);
 tc_status tc_alg_numerator(const tc_graph *g, uint64_t *d_num, hipStream_t s);  // tc_algebraic.hip
 tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s);
 tc_status tc_mid_prepare(tc_graph *g, hipStream_t s);

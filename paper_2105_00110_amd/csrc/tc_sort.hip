@@ -33,6 +33,11 @@ template <typename K, typename V, bool HAS_VAL>
 constexpr int sort_items() {
     return (sizeof(K) + (HAS_VAL ? sizeof(V) : 0)) <= 8 ? 32 : 16;
 }
+// Below this many elements the big tiles would leave CUs idle: 8 keys per
+// thread (tiles of 2048) instead.
+constexpr int64_t SORT_BIG_TILES_MIN = (int64_t)1 << 22;
+constexpr int SORT_SMALL_ITEMS = 8;
+
 static_assert(SORT_BLOCK == RADIX, "one digit per thread in the scatter's digit scans");
 
 struct NoVal {};
@@ -194,6 +199,18 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_radix_scatter(
     }
 }
 
+template <typename K, typename V, bool HAS_VAL, int ITEMS>
+tc_status radix_pass(const K *in, const V *vin, K *kout, V *vout, int64_t n, int shift,
+                     uint32_t *counts, int64_t tiles, const uint32_t *vhi, hipStream_t s) {
+    k_radix_hist<K, ITEMS><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(in, n, shift, counts, tiles);
+    TC_LAUNCHED();
+    TC_TRY(tc_scan_u32(counts, counts, tiles * RADIX, nullptr, s));
+    k_radix_scatter<K, V, HAS_VAL, ITEMS><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(
+        in, vin, kout, vout, n, shift, counts, tiles, vhi);
+    TC_LAUNCHED();
+    return TC_OK;
+}
+
 // src, when given, is read by the first pass in place of *keys (which then
 // needs no contents); with iota the first pass takes each element's index as
 // its value in place of *vals.  *keys and *tkeys are ping-pong buffers as
@@ -208,19 +225,22 @@ tc_status radix_sort(K **keys, V **vals, K **tkeys, V **tvals, int64_t n, int bi
     if (fresh && bits == 0) bits = 1;  // keys below 2^0 are all zero: one pass keeps the order
     if (n >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
     constexpr int ITEMS = sort_items<K, V, HAS_VAL>();
-    int64_t tiles = tc_div_up(n, (int64_t)SORT_BLOCK * ITEMS);
+    const bool big = n >= SORT_BIG_TILES_MIN;
+    int64_t tiles = tc_div_up(n, (int64_t)SORT_BLOCK * (big ? ITEMS : SORT_SMALL_ITEMS));
     tc_scratch tmp(s);
     uint32_t *counts = nullptr;
     TC_TRY(tmp.get(&counts, tiles * RADIX));
     for (int shift = 0; shift < bits; shift += RB) {
         const K *in = (src && shift == 0) ? src : *keys;
         const V *vin = (HAS_VAL && !(iota && shift == 0)) ? *vals : nullptr;
-        k_radix_hist<K, ITEMS><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(in, n, shift, counts, tiles);
-        TC_LAUNCHED();
-        TC_TRY(tc_scan_u32(counts, counts, tiles * RADIX, nullptr, s));
-        k_radix_scatter<K, V, HAS_VAL, ITEMS><<<(unsigned)tiles, SORT_BLOCK, 0, s>>>(
-            in, vin, *tkeys, HAS_VAL ? *tvals : nullptr, n, shift, counts, tiles,
-            shift == 0 ? vhi : nullptr);
+        V *vout = HAS_VAL ? *tvals : nullptr;
+        const uint32_t *vh = shift == 0 ? vhi : nullptr;
+        if (big)
+            TC_TRY((radix_pass<K, V, HAS_VAL, ITEMS>(in, vin, *tkeys, vout, n, shift, counts, tiles,
+                                                     vh, s)));
+        else
+            TC_TRY((radix_pass<K, V, HAS_VAL, SORT_SMALL_ITEMS>(in, vin, *tkeys, vout, n, shift,
+                                                                counts, tiles, vh, s)));
         TC_LAUNCHED();
         K *tk = *keys;
         *keys = *tkeys;
