@@ -560,6 +560,9 @@ __device__ __forceinline__ uint32_t stripe_bits(int o, uint32_t lo, uint32_t hi)
 constexpr int FOLD_RC = 63;  // rows per flush: 6 counter planes hold up to 63
 
 // One row u of the big-row fold; rb = B_u's first word, sup = u's supports.
+// The LDS counter of column j sits at j + j / 32 (one pad word per 32): at a
+// flush, lane c adds to 33 c + b, so neighbouring stripes hit different
+// banks.
 template <typename I>
 __device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I d, bool in_lds,
                                              uint32_t *__restrict__ colc,
@@ -580,7 +583,7 @@ __device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I 
                 for (int e = 0; e < 8; ++e) c += __popc(x[e]);
             }
         }
-        if (in_lds) colc[i] = c;
+        if (in_lds) colc[i + (i >> 5)] = c;
         else if (c) atomicAdd(&sup[i], c);
     }
     // column sums: lane (stripe c, row group g) of a group of up to 64
@@ -653,7 +656,7 @@ __device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I 
             for (int b = 0; b < 32; ++b) {
                 const I j = 32 * c + b;
                 if (j < d && cnt[b]) {
-                    if (in_lds) atomicAdd(&colc[j], cnt[b]);
+                    if (in_lds) atomicAdd(&colc[33 * c + b], cnt[b]);  // padded index of j
                     else atomicAdd(&sup[j], cnt[b]);
                 }
             }
@@ -661,11 +664,19 @@ __device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I 
     }
     if (in_lds)
         for (I j = lane; j < d; j += TC_WAVE) {
-            const uint32_t v = colc[j];
+            const uint32_t v = colc[j + (j >> 5)];
             if (v) sup[j] += v;  // the wavefront owns row u's slots here
         }
 }
 
+// LDS words of one wavefront's column counters for rows up to dcap entries.
+__host__ __device__ __forceinline__ size_t fold_colc_words(int dcap) {
+    return (size_t)dcap + ((size_t)dcap >> 5) + 1;
+}
+
+// One kernel per index type: rows below FOLD_I32_MAX entries (I = int32_t)
+// or from it up (int64_t); each skips the other's rows of the list.
+template <typename I>
 __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ rows, int64_t nrows,
                                                   const int64_t *__restrict__ orp,
                                                   const int64_t *__restrict__ rowbase,
@@ -673,7 +684,7 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
                                                   uint32_t *__restrict__ osup, int dcap) {
     extern __shared__ uint32_t colc_all[];
     const int wv = threadIdx.x / TC_WAVE;
-    uint32_t *colc = colc_all + (size_t)wv * dcap;
+    uint32_t *colc = colc_all + (size_t)wv * fold_colc_words(dcap);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / TC_WAVE);
     for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x / TC_WAVE) + wv; gi < nrows; gi += waves) {
         // the list is in rank order and the longest rows rank highest: take
@@ -681,12 +692,8 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
         const int32_t r = rows[nrows - 1 - gi];
         const int64_t rs = orp[r];
         const int64_t d = orp[r + 1] - rs;
-        const uint32_t *rb = bits + rowbase[r];
-        const bool in_lds = d <= dcap;
-        if (d < FOLD_I32_MAX)
-            fold_big_row<int32_t>(rb, (int32_t)d, in_lds, colc, osup + rs);
-        else
-            fold_big_row<int64_t>(rb, d, in_lds, colc, osup + rs);
+        if ((d < FOLD_I32_MAX) != (sizeof(I) == 4)) continue;
+        fold_big_row<I>(bits + rowbase[r], (I)d, d <= dcap, colc, osup + rs);
     }
 }
 
@@ -1012,12 +1019,20 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         }
         if (nb > 0) {
             int64_t fb = tc_div_up(nb, BK / TC_WAVE);
-            int dcap = g->max_dplus < 8192 ? g->max_dplus : 8192;
+            // LDS counters for rows up to 7936 entries: 4 wavefronts x
+            // fold_colc_words(7936) words stay within 128 KB
+            int dcap = g->max_dplus < 7936 ? g->max_dplus : 7936;
             dcap = (dcap + 3) & ~3;
-            k_fold_big<<<(unsigned)(fb < 1048576 ? fb : 1048576), BK,
-                         (size_t)(BK / TC_WAVE) * dcap * sizeof(uint32_t), s>>>(
+            k_fold_big<int32_t><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK,
+                                  (size_t)(BK / TC_WAVE) * fold_colc_words(dcap) * sizeof(uint32_t), s>>>(
                 big, nb, g->orp, g->rowbase, g->hitbits, g->osup, dcap);
             TC_LAUNCHED();
+            if (g->max_dplus >= FOLD_I32_MAX) {
+                k_fold_big<int64_t><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK,
+                                      (size_t)(BK / TC_WAVE) * fold_colc_words(dcap) * sizeof(uint32_t), s>>>(
+                    big, nb, g->orp, g->rowbase, g->hitbits, g->osup, dcap);
+                TC_LAUNCHED();
+            }
         }
     }
     tc_prof_mark(g, 9, s);
