@@ -231,7 +231,8 @@ __global__ void k_run_len64(int32_t n, const uint32_t *__restrict__ s, const uin
 //           ocol/o2e, with the row of every slot in orow.
 // ---------------------------------------------------------------------------
 constexpr int SEG_MAX = 4096;
-constexpr int SEG_WAVE = 64;  // buckets up to this many entries: one wavefront
+constexpr int SEG_WAVE = 64;    // buckets up to this many entries: a group of lanes each
+constexpr int SEG_SMALL = 256;  // up to this many: k_orient_small; above: bitonic sorts
 
 // Lanes hold consecutive elements of a sequence sorted by x (x is the same
 // for neighbouring lanes of one run); the active ones store their entry in
@@ -331,10 +332,11 @@ __global__ void k_dplus_by_rank(int32_t n, const uint32_t *__restrict__ cursor,
     if (__lane_id() == 0 && mx) atomicMax(dmax, mx);
 }
 
-// Buckets of 1..SEG_WAVE entries.  Every wavefront reads the sizes of 64
+// Buckets of 1..SEG_SMALL entries.  Every wavefront reads the sizes of 64
 // consecutive vertices and sorts their buckets by size class (lo, GL],
 // GL = 8, 16, 32, 64: GL lanes per bucket, 64 / GL buckets at a time, taken
-// from the ballot of the class.  Each lane places its entry by the number of
+// from the ballot of the class (classes (64, 128] and (128, 256]: the whole
+// wavefront, orient_class_wide).  Each lane places its entry by the number of
 // smaller keys in its group (keys of a bucket are distinct ranks).  The grid
 // strides over the vertices, so there is no wavefront per vertex to
 // dispatch.
@@ -383,12 +385,68 @@ __device__ __forceinline__ void orient_class(int64_t x0, uint32_t dl, uint32_t l
     }
 }
 
+// Buckets of lo < d <= 64 E entries: the whole wavefront, E entries per
+// lane, each placed by counting the smaller keys (the keys are read back from
+// LDS one at a time, the same word for every lane).
+template <int E>
+__device__ __forceinline__ void orient_class_wide(int64_t x0, uint32_t dl, uint32_t lo,
+                                                  uint32_t *wsk, const int64_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ rank,
+                                                  const int64_t *__restrict__ orp,
+                                                  const uint64_t *__restrict__ tbuf,
+                                                  int32_t *__restrict__ ocol,
+                                                  uint32_t *__restrict__ o2e,
+                                                  int32_t *__restrict__ orow) {
+    const int lane = __lane_id();
+    uint64_t mask = __ballot(dl > lo && dl <= (uint32_t)(TC_WAVE * E));
+    while (mask) {
+        const int j = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        const int d = (int)__shfl(dl, j, TC_WAVE);
+        const int64_t x = x0 + j;
+        const int64_t b = row_ptr[x];
+        uint32_t key[E], val[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = lane + TC_WAVE * e;
+            key[e] = 0xFFFFFFFFu;
+            val[e] = 0;
+            if (i < d) {
+                const uint64_t w = tbuf[b + i];
+                key[e] = (uint32_t)(w >> 32);
+                val[e] = (uint32_t)w;
+            }
+            wsk[i] = key[e];
+        }
+        __builtin_amdgcn_wave_barrier();
+        int pos[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) pos[e] = 0;
+        for (int t = 0; t < d; ++t) {
+            const uint32_t kt = wsk[t];
+#pragma unroll
+            for (int e = 0; e < E; ++e) pos[e] += kt < key[e] ? 1 : 0;
+        }
+        const int32_t rx = rank[x];
+        const int64_t ob = orp[rx];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (lane + TC_WAVE * e < d) {
+                ocol[ob + pos[e]] = (int32_t)key[e];
+                o2e[ob + pos[e]] = val[e];
+                orow[ob + pos[e]] = rx;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 __global__ __launch_bounds__(256) void k_orient_small(
     int32_t n, const int64_t *__restrict__ row_ptr, const uint32_t *__restrict__ cursor,
     const int32_t *__restrict__ rank, const int64_t *__restrict__ orp,
     const uint64_t *__restrict__ tbuf, int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
     int32_t *__restrict__ orow) {
-    __shared__ uint32_t sk[4][TC_WAVE];
+    __shared__ uint32_t sk[4][SEG_SMALL];
     const int wv = threadIdx.x / TC_WAVE;
     const int lane = __lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * 4;
@@ -399,6 +457,8 @@ __global__ __launch_bounds__(256) void k_orient_small(
         orient_class<16>(x0, dl, 8, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
         orient_class<32>(x0, dl, 16, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
         orient_class<64>(x0, dl, 32, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
+        orient_class_wide<2>(x0, dl, 64, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
+        orient_class_wide<4>(x0, dl, 128, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
     }
 }
 
@@ -448,7 +508,7 @@ __global__ __launch_bounds__(256) void k_orient_block(
     }
 }
 
-// One wavefront per listed vertex with SEG_WAVE < entries <= SEG_MID: the
+// One wavefront per listed vertex with SEG_SMALL < entries <= SEG_MID: the
 // same bitonic sort over an LDS buffer of the wavefront's own, so its rounds
 // need no workgroup barrier (a wavefront's LDS operations stay in order).
 constexpr int SEG_MID = 1024;
@@ -580,7 +640,7 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
     TC_LAUNCHED();
     // the buckets sorted by a wavefront and by a workgroup, listed now so that
     // one read-back brings their counts with the largest d+
-    k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_WAVE, SEG_MID, flags);
+    k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_SMALL, SEG_MID, flags);
     TC_LAUNCHED();
     TC_TRY(compact_vertices(n, flags, list_mid, info + 1, s));
     k_size_flags<<<grid_for(n), BK, 0, s>>>(n, cursor, SEG_MID, 0xFFFFFFFFu, flags2);
