@@ -36,6 +36,7 @@
 // workgroup table; pivots whose table does not fit LDS probe N_H(v) by
 // binary search in device memory.
 #include "tc_internal.h"
+#include <stdlib.h>
 #include "tc_table.h"
 
 namespace {
@@ -674,14 +675,16 @@ __host__ __device__ __forceinline__ size_t fold_colc_words(int dcap) {
     return (size_t)dcap + ((size_t)dcap >> 5) + 1;
 }
 
-// One kernel per index type: rows below FOLD_I32_MAX entries (I = int32_t)
-// or from it up (int64_t); each skips the other's rows of the list.
+// One kernel per index type: rows below i32_max entries (I = int32_t; at
+// most FOLD_I32_MAX) or from it up (int64_t); each skips the other's rows of
+// the list.
 template <typename I>
 __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ rows, int64_t nrows,
                                                   const int64_t *__restrict__ orp,
                                                   const int64_t *__restrict__ rowbase,
                                                   const uint32_t *__restrict__ bits,
-                                                  uint32_t *__restrict__ osup, int dcap) {
+                                                  uint32_t *__restrict__ osup, int dcap,
+                                                  int64_t i32_max) {
     extern __shared__ uint32_t colc_all[];
     const int wv = threadIdx.x / TC_WAVE;
     uint32_t *colc = colc_all + (size_t)wv * fold_colc_words(dcap);
@@ -692,7 +695,7 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
         const int32_t r = rows[nrows - 1 - gi];
         const int64_t rs = orp[r];
         const int64_t d = orp[r + 1] - rs;
-        if ((d < FOLD_I32_MAX) != (sizeof(I) == 4)) continue;
+        if ((d < i32_max) != (sizeof(I) == 4)) continue;
         fold_big_row<I>(bits + rowbase[r], (I)d, d <= dcap, colc, osup + rs);
     }
 }
@@ -1023,14 +1026,21 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
             // fold_colc_words(7936) words stay within 128 KB
             int dcap = g->max_dplus < 7936 ? g->max_dplus : 7936;
             dcap = (dcap + 3) & ~3;
-            k_fold_big<int32_t><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK,
-                                  (size_t)(BK / TC_WAVE) * fold_colc_words(dcap) * sizeof(uint32_t), s>>>(
-                big, nb, g->orp, g->rowbase, g->hitbits, g->osup, dcap);
+            // TC_FOLD_I32_MAX (environment) lowers the row length from which
+            // the 64-bit kernel folds, so that its path can be exercised on
+            // small graphs
+            int64_t i32_max = FOLD_I32_MAX;
+            if (const char *ev = getenv("TC_FOLD_I32_MAX")) {
+                const long v = strtol(ev, nullptr, 10);
+                if (v >= 0 && v < FOLD_I32_MAX) i32_max = v;
+            }
+            const size_t lds = (size_t)(BK / TC_WAVE) * fold_colc_words(dcap) * sizeof(uint32_t);
+            k_fold_big<int32_t><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK, lds, s>>>(
+                big, nb, g->orp, g->rowbase, g->hitbits, g->osup, dcap, i32_max);
             TC_LAUNCHED();
-            if (g->max_dplus >= FOLD_I32_MAX) {
-                k_fold_big<int64_t><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK,
-                                      (size_t)(BK / TC_WAVE) * fold_colc_words(dcap) * sizeof(uint32_t), s>>>(
-                    big, nb, g->orp, g->rowbase, g->hitbits, g->osup, dcap);
+            if (g->max_dplus >= i32_max) {
+                k_fold_big<int64_t><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK, lds, s>>>(
+                    big, nb, g->orp, g->rowbase, g->hitbits, g->osup, dcap, i32_max);
                 TC_LAUNCHED();
             }
         }

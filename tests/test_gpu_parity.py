@@ -349,6 +349,23 @@ def test_big_clique_fold_two_stripe_groups(tclib):
     assert np.all(r["tc"] == 1.0)
 
 
+def test_fold_64bit_offsets_path(tclib, monkeypatch):
+    # rows of 32768 entries and more fold with 64-bit offsets inside their
+    # bit matrix; lower that switch so the path runs on a small graph: every
+    # fold row through it (0), and rows from 100 entries up (both kernels in
+    # one compute)
+    src, dst, n = gg.rmat(13, 16, seed=41)
+    ks, kd, kn = gg.clique(300)
+    src = np.concatenate([src, ks + n]).astype(np.int32)
+    dst = np.concatenate([dst, kd + n]).astype(np.int32)
+    n = n + kn
+    ref = native.o1_definition(src, dst, n)
+    for lim in ("0", "100"):
+        monkeypatch.setenv("TC_FOLD_I32_MAX", lim)
+        _say("fold with 64-bit offsets from", lim, "entries")
+        assert_parity(run_gpu(tclib, src, dst, n, tuning={"algorithm": 2}), ref)
+
+
 def test_auto_pivot_choice(tclib):
     # TC_ALGO_AUTO: the low pivot for small graphs, the middle pivot from
     # 600000 edges up; the work statistics report the form that ran
