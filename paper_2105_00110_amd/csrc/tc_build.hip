@@ -68,38 +68,107 @@ __global__ void k_make_keys(const int32_t *__restrict__ src, const int32_t *__re
     }
 }
 
-__global__ void k_unique_flags(const uint64_t *__restrict__ keys, int64_t P, uint64_t sentinel,
-                               uint32_t *__restrict__ flags) {
-    GRID_STRIDE(i, P) {
-        uint64_t k = keys[i];
-        flags[i] = (k != sentinel && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+// Deduplication as a two-pass compaction over tiles of UQ_TILE sorted keys:
+// k_unique_count counts each tile's canonical edges (the first key of every
+// run of equal keys, sentinels excluded), the tile counts are scanned, and
+// k_unique_emit recomputes the flags, places them by a workgroup scan and
+// stores the tile's edges side by side.  Every key is read twice and every
+// edge written once; no per-key flag or position array goes to memory.
+constexpr int UQ_BLOCK = 256;
+constexpr int UQ_ITEMS = 16;
+constexpr int UQ_TILE = UQ_BLOCK * UQ_ITEMS;
+
+__device__ __forceinline__ bool first_of_run(const uint64_t *__restrict__ keys, int64_t i,
+                                             uint64_t k, uint64_t sentinel) {
+    return k != sentinel && (i == 0 || keys[i - 1] != k);
+}
+
+__global__ __launch_bounds__(UQ_BLOCK) void k_unique_count(const uint64_t *__restrict__ keys,
+                                                           int64_t P, uint64_t sentinel,
+                                                           uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t red[UQ_BLOCK / TC_WAVE];
+    const int64_t base = (int64_t)blockIdx.x * UQ_TILE;
+    uint32_t c = 0;
+#pragma unroll
+    for (int it = 0; it < UQ_ITEMS; ++it) {
+        const int64_t i = base + it * UQ_BLOCK + threadIdx.x;
+        if (i < P) c += first_of_run(keys, i, keys[i], sentinel) ? 1u : 0u;
+    }
+    c = tc_wave_sum(c);
+    if (__lane_id() == 0) red[threadIdx.x / TC_WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < UQ_BLOCK / TC_WAVE; ++w) t += red[w];
+        cnt[blockIdx.x] = t;
     }
 }
 
-// Writes the canonical edges (first key of every run of equal keys) and, in
-// the same pass, the run [us[u], ue[u]) of the edges whose smaller end is u
-// (edges come sorted by it).  us and ue start zeroed; the end of the last
-// run is set by k_last_run.
-__global__ void k_unique_write(const uint64_t *__restrict__ keys, int64_t P, uint64_t sentinel,
-                               int bits, const uint32_t *__restrict__ pos,
-                               int32_t *__restrict__ eu, int32_t *__restrict__ ev,
-                               uint32_t *__restrict__ us, uint32_t *__restrict__ ue) {
+// Writes the canonical edges of each tile at tile_off[tile] and, in the same
+// pass, the run [us[u], ue[u]) of the edges whose smaller end is u (edges
+// come sorted by it).  us and ue start zeroed; the end of the last run is set
+// by k_last_run.
+__global__ __launch_bounds__(UQ_BLOCK) void k_unique_emit(const uint64_t *__restrict__ keys,
+                                                          int64_t P, uint64_t sentinel, int bits,
+                                                          const uint32_t *__restrict__ tile_off,
+                                                          int32_t *__restrict__ eu,
+                                                          int32_t *__restrict__ ev,
+                                                          uint32_t *__restrict__ us,
+                                                          uint32_t *__restrict__ ue) {
+    constexpr int W = UQ_BLOCK / TC_WAVE;
+    __shared__ int32_t su[UQ_TILE], sv[UQ_TILE];
+    __shared__ uint32_t cnt[UQ_ITEMS * W];  // flags per (item, wavefront), then their prefix
+    __shared__ uint32_t total;
     const uint64_t mask = (1ull << bits) - 1;
-    GRID_STRIDE(i, P) {
-        uint64_t k = keys[i];
-        const uint64_t prev = i > 0 ? keys[i - 1] : sentinel;
-        if (k != sentinel && prev != k) {
-            const uint32_t p = pos[i];
-            const uint32_t u = (uint32_t)(k >> bits), v = (uint32_t)(k & mask);
-            eu[p] = (int32_t)u;
-            ev[p] = (int32_t)v;
+    const int64_t base = (int64_t)blockIdx.x * UQ_TILE;
+    const int w = threadIdx.x / TC_WAVE;
+    const int lane = __lane_id();
+    const uint64_t lt = tc_lanemask_lt();
+    // element it * UQ_BLOCK + threadIdx.x of the tile: a wavefront holds 64
+    // consecutive elements per item, and tile order is (item, wavefront, lane)
+    uint64_t k[UQ_ITEMS], prev[UQ_ITEMS], fl[UQ_ITEMS];
+#pragma unroll
+    for (int it = 0; it < UQ_ITEMS; ++it) {
+        const int64_t i = base + it * UQ_BLOCK + threadIdx.x;
+        k[it] = i < P ? keys[i] : sentinel;
+        prev[it] = (i > 0 && i < P) ? keys[i - 1] : sentinel;
+        fl[it] = __ballot(k[it] != sentinel && (i == 0 || prev[it] != k[it]));
+        if (lane == 0) cnt[it * W + w] = (uint32_t)__popcll(fl[it]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int q = 0; q < UQ_ITEMS * W; ++q) {
+            const uint32_t c = cnt[q];
+            cnt[q] = run;
+            run += c;
+        }
+        total = run;
+    }
+    __syncthreads();
+    const uint32_t p0 = tile_off[blockIdx.x];
+#pragma unroll
+    for (int it = 0; it < UQ_ITEMS; ++it) {
+        if ((fl[it] >> lane) & 1ull) {
+            const uint32_t lp = cnt[it * W + w] + (uint32_t)__popcll(fl[it] & lt);
+            const uint32_t u = (uint32_t)(k[it] >> bits), v = (uint32_t)(k[it] & mask);
+            su[lp] = (int32_t)u;
+            sv[lp] = (int32_t)v;
             // prev is the previous distinct key (sentinels sort last)
-            const uint32_t pu = (uint32_t)(prev >> bits);
-            if (i == 0 || pu != u) {
-                us[u] = p;
-                if (i > 0) ue[pu] = p;
+            const uint32_t pu = (uint32_t)(prev[it] >> bits);
+            if (base + it * UQ_BLOCK + threadIdx.x == 0) {
+                us[u] = 0;
+            } else if (pu != u) {
+                us[u] = p0 + lp;
+                ue[pu] = p0 + lp;
             }
         }
+    }
+    __syncthreads();
+    const uint32_t tot = total;
+    for (uint32_t j = threadIdx.x; j < tot; j += UQ_BLOCK) {
+        eu[p0 + j] = su[j];
+        ev[p0 + j] = sv[j];
     }
 }
 
@@ -722,12 +791,13 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
                                                num_graphs, keys, g->err);
         TC_LAUNCHED();
         TC_TRY(tc_sort_u64(&keys, &keys2, P, 2 * bits, s));
-        uint32_t *pos = nullptr, *d_m = nullptr;
-        TC_TRY(tmp.get(&pos, P));
+        const int64_t tiles = tc_div_up(P, UQ_TILE);
+        uint32_t *tcnt = nullptr, *d_m = nullptr;
+        TC_TRY(tmp.get(&tcnt, tiles));
         TC_TRY(tmp.get(&d_m, 1));
-        k_unique_flags<<<grid_for(P), BK, 0, s>>>(keys, P, sentinel, pos);
+        k_unique_count<<<(unsigned)tiles, UQ_BLOCK, 0, s>>>(keys, P, sentinel, tcnt);
         TC_LAUNCHED();
-        TC_TRY(tc_scan_u32(pos, pos, P, d_m, s));
+        TC_TRY(tc_scan_u32(tcnt, tcnt, tiles, d_m, s));
         uint32_t h_m = 0, h_err = 0;
         TC_HIP(hipMemcpyAsync(&h_err, g->err, 4, hipMemcpyDeviceToHost, s));
         TC_HIP(hipMemcpyAsync(&h_m, d_m, 4, hipMemcpyDeviceToHost, s));
@@ -737,8 +807,8 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
         TC_TRY(tc_graph_alloc(g, &g->eu, m, s));
         TC_TRY(tc_graph_alloc(g, &g->ev, m, s));
         if (m > 0) {
-            k_unique_write<<<grid_for(P), BK, 0, s>>>(keys, P, sentinel, bits, pos, g->eu, g->ev,
-                                                      us, ue);
+            k_unique_emit<<<(unsigned)tiles, UQ_BLOCK, 0, s>>>(keys, P, sentinel, bits, tcnt, g->eu,
+                                                               g->ev, us, ue);
             TC_LAUNCHED();
             k_last_run<<<1, 64, 0, s>>>(m, g->eu, ue);
             TC_LAUNCHED();
