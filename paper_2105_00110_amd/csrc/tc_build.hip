@@ -188,10 +188,6 @@ __global__ void k_runs(Get get, int64_t len, uint32_t *__restrict__ start,
     }
 }
 
-struct GetI32 {
-    const int32_t *a;
-    __device__ uint32_t operator()(int64_t i) const { return (uint32_t)a[i]; }
-};
 struct GetU32 {
     const uint32_t *a;
     __device__ uint32_t operator()(int64_t i) const { return a[i]; }

@@ -96,9 +96,6 @@ tc_status tc_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total
 // The sorted data ends in *keys / *vals: the pointers are swapped with the
 // tmp pointers when the pass count is odd, so callers free both buffers.
 tc_status tc_sort_u64(uint64_t **keys, uint64_t **tmp_keys, int64_t n, int bits, hipStream_t s);
-// keys only, the first pass reading src (left unchanged); the result is in *keys
-tc_status tc_sort_u32_from(const uint32_t *src, uint32_t **keys, uint32_t **tmp_keys, int64_t n,
-                           int bits, hipStream_t s);
 // keys from src (left unchanged), values the input positions 0..n-1: the
 // stable sorting permutation of src; the result is in *keys / *vals
 tc_status tc_sort_u32_index(const uint32_t *src, uint32_t **keys, uint32_t **vals,
@@ -112,8 +109,6 @@ tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s);
 tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s);
-tc_status tc_sort_u32_u64(uint32_t **keys, uint64_t **vals, uint32_t **tmp_keys,
-                          uint64_t **tmp_vals, int64_t n, int bits, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // The graph handle.

@@ -261,11 +261,6 @@ tc_status tc_sort_u64(uint64_t **keys, uint64_t **tmp_keys, int64_t n, int bits,
     return radix_sort<uint64_t, uint32_t, false>(keys, &nv, tmp_keys, &ntv, n, bits, s);
 }
 
-tc_status tc_sort_u32_from(const uint32_t *src, uint32_t **keys, uint32_t **tmp_keys, int64_t n,
-                           int bits, hipStream_t s) {
-    uint32_t *nv = nullptr, *ntv = nullptr;
-    return radix_sort<uint32_t, uint32_t, false>(keys, &nv, tmp_keys, &ntv, n, bits, s, src);
-}
 
 tc_status tc_sort_u32_index(const uint32_t *src, uint32_t **keys, uint32_t **vals,
                             uint32_t **tmp_keys, uint32_t **tmp_vals, int64_t n, int bits,
@@ -291,7 +286,3 @@ tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,
     return radix_sort<uint32_t, uint32_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s);
 }
 
-tc_status tc_sort_u32_u64(uint32_t **keys, uint64_t **vals, uint32_t **tmp_keys,
-                          uint64_t **tmp_vals, int64_t n, int bits, hipStream_t s) {
-    return radix_sort<uint32_t, uint64_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s);
-}
