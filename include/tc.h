@@ -217,8 +217,11 @@ tc_status tc_get_results(const tc_graph *g, uint64_t *tri, uint64_t *support, ui
  * kernel with tc_compute's aggregation (Algorithm 2), so num[] here equals
  * tc_get_results' num[] exactly; tests use it as a cross-check.
  * num[n] (uint64, vertex order; per batch, concatenated like tri[]).  The
- * call allocates 4*2m + 16*n bytes of stream-ordered scratch and, with
- * TC_MEM_HOST, returns after the copy.  TC_ERR_NOT_COMPUTED before
+ * first call on a handle fills its symmetric adjacency (16*m bytes, held by
+ * the handle until destroyed; after a middle-pivot tc_compute this first
+ * sorts the edges by their larger end, with 16*m bytes of scratch).  Every
+ * call allocates 4*2m + 16*n bytes of scratch and, with TC_MEM_HOST,
+ * returns after the copy.  TC_ERR_NOT_COMPUTED before
  * tc_compute; TC_ERR_DEVICE if a product comes out odd (it cannot if the
  * support is a valid T). */
 tc_status tc_numerator_algebraic(const tc_graph *g, uint64_t *num, int32_t mem_kind, void *stream);
@@ -299,7 +302,7 @@ tc_status tc_top_k(const tc_graph *g, int32_t k, int32_t *vertices, double *valu
  * ---------------------------------------------------------------------- */
 #define TC_NUM_STAGES 10
 enum {
-    TC_STAGE_CSR_BUILD = 0,   /* dedup + symmetric CSR                  */
+    TC_STAGE_CSR_BUILD = 0,   /* dedup, degrees, symmetric row offsets  */
     TC_STAGE_DEGREE_RANK = 1, /* degree ordering                        */
     TC_STAGE_ORIENT = 2,      /* oriented CSR over ranks                */
     TC_STAGE_BIN = 3,         /* row binning by |N_H(v)| (+ transposed
@@ -308,7 +311,8 @@ enum {
     TC_STAGE_COUNT_HEAVY = 5, /* intersection, workgroup per row (LDS)  */
     TC_STAGE_COUNT_HUGE = 6,  /* intersection, device-memory probe      */
     TC_STAGE_FOLD = 7,        /* bit-matrix fold (middle pivot only)    */
-    TC_STAGE_TRI = 8,         /* support per edge, tri(v), triG         */
+    TC_STAGE_TRI = 8,         /* support per edge, tri(v), triG (after
+                                 the low pivot: + symmetric adjacency)   */
     TC_STAGE_AGGREGATE = 9    /* Algorithm 2 sums + quotient            */
 };
 #define TC_NUM_WORK_STATS 17
