@@ -45,6 +45,9 @@ using namespace tc_tab;
 
 constexpr int BK = 256;
 constexpr size_t GROUP_BYTES = 64 * 8 * 3 + 64 * 4;  // gx, gs, gb (int64), gt (int32)
+constexpr int GROUP_LANES = 16;  // lanes per short pivot (k_mid_groups)
+constexpr int GROUP_DMAX = 128;  // rows up to this many entries go to k_mid_groups
+constexpr int GROUP_PAIRS = 64;  // pairs per k_mid_groups item
 
 // Words of the bit rows of a row with d entries: Σ_{t=1}^{d-1} ceil(t/32).
 __host__ __device__ __forceinline__ int64_t bit_words(int64_t d) {
@@ -195,7 +198,9 @@ __device__ void bitmap_build(uint2 *bm, uint32_t *scan, const int32_t *__restric
 // 64).  gx/gs/gb/gt: this wavefront's LDS arrays (exclusive scan of word
 // counts, scan starts, bit-row bases, tail lengths).
 // ---------------------------------------------------------------------------
-template <int LK>
+// GL lanes take the group (a whole wavefront for GL = 64, or one of its
+// 64 / GL groups, each with its own arrays and counters); at most GL pairs.
+template <int LK, int GL = TC_WAVE>
 __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                                           const int32_t *__restrict__ ocol,
                                           const uint64_t *__restrict__ in_pair,
@@ -206,7 +211,8 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                                           int64_t *gs, int64_t *gb, int32_t *gt,
                                           uint32_t *__restrict__ bits, uint32_t *__restrict__ osup,
                                           unsigned long long &found) {
-    const int lane = __lane_id();
+    static_assert(GL <= TC_WAVE && TC_WAVE % GL == 0, "group width");
+    const int lane = __lane_id() % GL;
     const int64_t i = g0 + lane;
     int64_t words = 0;
     if (i < gend) {
@@ -222,13 +228,22 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
         gb[lane] = rowbase[u] + bit_words(d) - bit_words(d - ii);
         gt[lane] = (int32_t)tail;
     }
-    const int64_t incl = tc_wave_incl_scan(words);
-    const int64_t total = __shfl(incl, TC_WAVE - 1, TC_WAVE);
+    int64_t incl = words;
+    if constexpr (GL == TC_WAVE) {
+        incl = tc_wave_incl_scan(words);
+    } else {
+#pragma unroll
+        for (int off = 1; off < GL; off <<= 1) {
+            const int64_t t = __shfl_up(incl, off, GL);
+            if (lane >= off) incl += t;
+        }
+    }
+    const int64_t total = __shfl(incl, GL - 1, GL);
     gx[lane] = incl - words;
-    for (int64_t base = 0; base < total; base += TC_WAVE) {
+    for (int64_t base = 0; base < total; base += GL) {
         const int64_t x = base + lane;
         if (x < total) {
-            int lo = 0, hi = TC_WAVE - 1;  // last pair p with gx[p] <= x
+            int lo = 0, hi = GL - 1;  // last pair p with gx[p] <= x
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (gx[mid] <= x) lo = mid; else hi = mid - 1;
@@ -348,6 +363,67 @@ static inline size_t mid_block_bytes(int dmax, int wpb, int lk, int bitmap_words
     if (lk == LK_HASH) t = table_bytes(dmax) + counter_bytes(dmax);
     if (lk == LK_BITMAP) t = 8 * (size_t)bitmap_words + counter_bytes(dmax) + 64;
     return t + (size_t)wpb * GROUP_BYTES;
+}
+
+// Several short pivots per wavefront: groups of GL lanes each take one item
+// (pivot rows of at most dcap entries, items of a few pairs), with their own
+// LDS table, counters and pair arrays; mid_group runs on the group.  Short
+// pivots have a few words of candidates per item, so a whole wavefront per
+// item would leave most lanes idle.
+__host__ __device__ __forceinline__ size_t mid_group_bytes(int dcap, int gl) {
+    return table_bytes(dcap) + counter_bytes(dcap) + (size_t)gl * (8 * 3 + 4);
+}
+
+template <int GL>
+__global__ __launch_bounds__(256, 4) void k_mid_groups(const int64_t *__restrict__ orp,
+                                                    const int32_t *__restrict__ ocol,
+                                                    const int64_t *__restrict__ in_ptr,
+                                                    const uint64_t *__restrict__ in_pair,
+                                                    const int64_t *__restrict__ rowbase,
+                                                    uint32_t *__restrict__ bits,
+                                                    const int32_t *__restrict__ item_v,
+                                                    const uint32_t *__restrict__ item_first,
+                                                    int64_t nitems, int dcap, int item_pairs,
+                                                    uint32_t *__restrict__ osup,
+                                                    unsigned long long *__restrict__ tri_total) {
+    extern __shared__ uint4 lds4[];
+    const int gpb = blockDim.x / GL;
+    const int gi = threadIdx.x / GL;
+    const int lane = threadIdx.x % GL;
+    char *base = reinterpret_cast<char *>(lds4) + (size_t)gi * mid_group_bytes(dcap, GL);
+    const size_t tb = table_bytes(dcap);
+    const size_t nbmax = (size_t)1 << bucket_bits(dcap);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(base);
+    uint16_t *pos = reinterpret_cast<uint16_t *>(base + 16 * nbmax);
+    uint32_t *lsup = reinterpret_cast<uint32_t *>(base + tb);
+    char *grp = base + tb + counter_bytes(dcap);
+    int64_t *gx = reinterpret_cast<int64_t *>(grp);
+    int64_t *gs = gx + GL;
+    int64_t *gb = gs + GL;
+    int32_t *gt = reinterpret_cast<int32_t *>(gb + GL);
+    unsigned long long found = 0;
+    for (int64_t it = (int64_t)blockIdx.x * gpb + gi; it < nitems; it += (int64_t)gridDim.x * gpb) {
+        const int32_t v = item_v[it];
+        const int64_t first = item_first[it];
+        const int64_t pend = min(first + (int64_t)item_pairs, in_ptr[v + 1]);
+        const int64_t vstart = orp[v];
+        const int d = (int)(orp[v + 1] - vstart);
+        const RowTable t{keys, pos, bucket_bits(d)};
+        for (int j = lane; j < (4 << t.bb); j += GL) keys[j] = EMPTY;
+        for (int j = lane; j < d; j += GL) lsup[j] = 0;
+        for (int j = lane; j < d; j += GL) table_insert(t, (uint32_t)ocol[vstart + j], j);
+        const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
+        for (int64_t g0 = first; g0 < pend; g0 += GL)
+            mid_group<LK_HASH, GL>(orp, ocol, in_pair, rowbase, g0, min(g0 + GL, pend), t,
+                                   BitmapRow{nullptr, 0, 0}, hmax, lsup, vstart, d, gx, gs, gb, gt,
+                                   bits, osup, found);
+        for (int j = lane; j < d; j += GL) {
+            const uint32_t c = lsup[j];
+            if (c) atomicAdd(&osup[vstart + j], c);
+        }
+    }
+    found = tc_wave_sum(found);
+    if (__lane_id() == 0 && found) atomicAdd(tri_total, found);
 }
 
 // One workgroup per item; its wavefronts share the pivot's lookup structure
@@ -915,9 +991,14 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     const int64_t span_max = 32 * (int64_t)bw;
     const int split = bw > 0 ? 1 : 0;
     const int lsplit = (bw > 0 && t.light_bitmap_pairs > 0) ? 1 : 0;
-    enum { P_WAVE, P_LBITMAP, P_BITMAP, P_BLOCK, P_HUGE, NPLANS };
+    // wavefront pivots with rows of at most GROUP_DMAX entries run
+    // 64 / GROUP_LANES to a wavefront, in items of at most GROUP_PAIRS pairs
+    const int gmax = light_max < GROUP_DMAX ? light_max : GROUP_DMAX;
+    const int group_pairs = wave_pairs < GROUP_PAIRS ? wave_pairs : GROUP_PAIRS;
+    enum { P_GROUP, P_WAVE, P_LBITMAP, P_BITMAP, P_BLOCK, P_HUGE, NPLANS };
     ItemPlan pl[NPLANS];
-    pl[P_WAVE] = {1, light_max, wave_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs};
+    pl[P_GROUP] = {1, gmax, group_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs};
+    pl[P_WAVE] = {gmax + 1, light_max, wave_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs};
     pl[P_LBITMAP] = {1, lsplit ? light_max : 0, block_pairs, 1, span_max, t.light_bitmap_pairs};
     pl[P_BITMAP] = {light_max + 1, split ? huge_min - 1 : light_max, block_pairs, 1, span_max, 0};
     pl[P_BLOCK] = {light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, 0};
@@ -944,6 +1025,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
             rp[i].count = h_tots[NPLANS + i];
             TC_TRY(rows_write(g, rp[i], items, s));
         }
+    const int64_t n_group = pl[P_GROUP].count;
     const int64_t n_wave = pl[P_WAVE].count, n_lbitmap = pl[P_LBITMAP].count;
     const int64_t n_bitmap = pl[P_BITMAP].count, n_block = pl[P_BLOCK].count;
     const int64_t n_huge = pl[P_HUGE].count;
@@ -952,7 +1034,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     uint32_t *wv_f = pl[P_WAVE].item_first, *lb_f = pl[P_LBITMAP].item_first;
     uint32_t *bm_f = pl[P_BITMAP].item_first, *bl_f = pl[P_BLOCK].item_first;
     uint32_t *hu_f = pl[P_HUGE].item_first;
-    g->n_light = n_wave + n_lbitmap;
+    g->n_light = n_group + n_wave + n_lbitmap;
     g->n_heavy = n_block + n_bitmap;
     g->n_huge = n_huge;
     // pairs whose pivot closes nothing are never scanned: their rows stay 0
@@ -963,6 +1045,15 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     }
     tc_prof_mark(g, 5, s);
 
+    if (n_group > 0) {
+        const int gpb = 256 / GROUP_LANES;
+        int64_t blocks = tc_div_up(n_group, gpb);
+        if (blocks > 262144) blocks = 262144;
+        k_mid_groups<GROUP_LANES><<<(unsigned)blocks, 256, (size_t)gpb * mid_group_bytes(gmax, GROUP_LANES), s>>>(
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, pl[P_GROUP].item_v,
+            pl[P_GROUP].item_first, n_group, gmax, group_pairs, g->osup, found);
+        TC_LAUNCHED();
+    }
     if (n_wave > 0) {
         const size_t per_wave = mid_wave_bytes(light_max);
         int wpb = t.light_block / TC_WAVE;
