@@ -58,13 +58,14 @@ static inline tc_status tc_alloc(T **p, int64_t count, hipStream_t s) {
 
 // Temporaries of one host function, released (stream-ordered) on exit.
 struct tc_scratch {
+    static constexpr int MAX = 64;
     hipStream_t s;
-    void *ptrs[32];
+    void *ptrs[MAX];
     int n = 0;
     explicit tc_scratch(hipStream_t st) : s(st) {}
     template <typename T>
     tc_status get(T **p, int64_t count) {
-        if (n >= 32) return TC_ERR_INVALID_ARG;
+        if (n >= MAX) return TC_ERR_INVALID_ARG;
         tc_status r = tc_alloc(p, count, s);
         if (r == TC_OK) ptrs[n++] = (void *)*p;
         return r;
