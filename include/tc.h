@@ -106,8 +106,10 @@ const char *tc_status_string(int32_t status);
  *                      above v is streamed (Procedure 1's inner loop);
  *                    TC_ALGO_AUTO (0) picks the middle pivot, whose
  *                    streamed work is the number of oriented wedges, for
- *                    graphs of 600000 edges or more, and the low pivot
- *                    below (fewer launches and host round trips).
+ *                    graphs of 600000 edges or more with an oriented row of
+ *                    32 entries or more, and for every graph of 3000000
+ *                    edges or more; the low pivot otherwise (fewer
+ *                    launches and host round trips).
  *                    In the middle-pivot form "rows" are the pivots v and
  *                    the bins above are taken on |N_H(v)| of the pivot.
  *   item_pairs       middle pivot only: lower neighbours of one pivot per

@@ -31,7 +31,12 @@ namespace {
 
 constexpr int BK = 256;
 constexpr int UNROLL = 4;  // independent candidate loads in flight per lane
-constexpr int64_t AUTO_LOW_PIVOT_MAX_EDGES = 600000;
+// TC_ALGO_AUTO takes the middle pivot from AUTO_MID_MIN_EDGES edges when
+// the orientation has a row of AUTO_MID_MIN_DPLUS entries or more (degree
+// skew), and from AUTO_MID_MIN_EDGES_FLAT edges otherwise
+constexpr int64_t AUTO_MID_MIN_EDGES = 600000;
+constexpr int64_t AUTO_MID_MIN_EDGES_FLAT = 3000000;
+constexpr int AUTO_MID_MIN_DPLUS = 32;
 using namespace tc_tab;
 
 static inline unsigned grid_for(int64_t n, int block = BK) {
@@ -306,10 +311,16 @@ tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
     while (max_entries > 1024 && heavy_bytes(max_entries / 2) > (size_t)lds_limit) max_entries >>= 1;
     // AUTO: the middle pivot streams fewer candidates (the oriented wedges),
     // but its transposition, work items and fold cost a fixed number of
-    // launches and host round trips; below AUTO_LOW_PIVOT_MAX_EDGES edges
-    // the low pivot finishes first on this device.
+    // launches and host round trips.  On this device the low pivot finishes
+    // first below about 0.6 M edges, and, on graphs whose oriented rows all
+    // stay short (no degree skew, e.g. ER at average degree 16), up to a few
+    // million.
     int algo = t.algorithm;
-    if (algo == TC_ALGO_AUTO) algo = m < AUTO_LOW_PIVOT_MAX_EDGES ? TC_ALGO_LOW_PIVOT : TC_ALGO_MID_PIVOT;
+    if (algo == TC_ALGO_AUTO) {
+        const bool mid = m >= AUTO_MID_MIN_EDGES_FLAT ||
+                         (m >= AUTO_MID_MIN_EDGES && g->max_dplus >= AUTO_MID_MIN_DPLUS);
+        algo = mid ? TC_ALGO_MID_PIVOT : TC_ALGO_LOW_PIVOT;
+    }
     g->algo_used = algo;
     if (algo == TC_ALGO_MID_PIVOT) return tc_count_mid(g, t, lds_limit, max_entries, found, s);
     const int light_max = t.light_max_dplus;

@@ -367,9 +367,12 @@ def test_fold_64bit_offsets_path(tclib, monkeypatch):
 
 
 def test_auto_pivot_choice(tclib):
-    # TC_ALGO_AUTO: the low pivot for small graphs, the middle pivot from
-    # 600000 edges up; the work statistics report the form that ran
+    # TC_ALGO_AUTO: the low pivot for small graphs and for flat ones (all
+    # oriented rows under 32 entries) below 3 M edges, the middle pivot from
+    # 600000 edges up on skewed graphs; the work statistics report the form
+    # that ran
     cases = [(gg.er(2000, 0.005, seed=1), tclib.TC_ALGO_LOW_PIVOT),
+             (gg.er(200000, 16.0 / 200000, seed=3), tclib.TC_ALGO_LOW_PIVOT),
              (gg.rmat(17, 16, seed=17), tclib.TC_ALGO_MID_PIVOT)]
     for (src, dst, n), want in cases:
         g = tclib.Graph.from_edges(torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n)
