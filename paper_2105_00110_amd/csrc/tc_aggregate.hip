@@ -62,6 +62,13 @@ __device__ __forceinline__ int32_t graph_of(const int64_t *__restrict__ vtx_off,
     return lo;
 }
 
+// esup[e[i]] = sup[i] for pairs already grouped by the top bits of e, so
+// that the stores of neighbouring blocks fall in a few narrow windows.
+__global__ void k_store_pairs(int64_t m, const uint32_t *__restrict__ e,
+                              const uint32_t *__restrict__ sup, uint32_t *__restrict__ esup) {
+    GRID_STRIDE(i, m) esup[e[i]] = sup[i];
+}
+
 __global__ void k_scatter_sup(int64_t m, const uint32_t *__restrict__ o2e,
                               const uint32_t *__restrict__ osup, uint32_t *__restrict__ esup) {
     GRID_STRIDE(k, m) esup[o2e[k]] = osup[k];
@@ -389,6 +396,30 @@ __global__ void k_big_write(int32_t n, const int64_t *__restrict__ row_ptr,
 
 static tc_status aggregate_rank_space(tc_graph *g, hipStream_t s);
 
+// esup (canonical edge order) from osup (oriented slot order).  Large
+// graphs first group the (edge, support) pairs by the top 8 bits of the
+// edge id with one stable radix pass, so the stores then land in windows of
+// about m / 256 edges instead of all over esup.
+static tc_status support_to_edge_order(tc_graph *g, hipStream_t s) {
+    const int64_t m = g->m;
+    if (m == 0) return TC_OK;
+    if (m < ((int64_t)1 << 22)) {
+        k_scatter_sup<<<grid_for(m), BK, 0, s>>>(m, g->o2e, g->osup, g->esup);
+        TC_LAUNCHED();
+        return TC_OK;
+    }
+    int ebits = 0;
+    while (((int64_t)1 << ebits) < m) ++ebits;
+    tc_scratch tmp(s);
+    uint32_t *e2 = nullptr, *s2 = nullptr;
+    TC_TRY(tmp.get(&e2, m));
+    TC_TRY(tmp.get(&s2, m));
+    TC_TRY(tc_partition_u32_u32(g->o2e, g->osup, e2, s2, m, ebits - 8, s));
+    k_store_pairs<<<grid_for(m), BK, 0, s>>>(m, e2, s2, g->esup);
+    TC_LAUNCHED();
+    return TC_OK;
+}
+
 tc_status tc_aggregate(tc_graph *g, hipStream_t s) {
     // with the transposed orientation at hand, aggregate in rank space; the
     // symmetric adjacency is then never filled
@@ -483,10 +514,7 @@ static tc_status aggregate_rank_space(tc_graph *g, hipStream_t s) {
     k_rank_chunk_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->in_ptr, cnt);
     TC_LAUNCHED();
     TC_TRY(tc_scan_u32(cnt, off, n, tot, s));
-    if (m > 0) {
-        k_scatter_sup<<<grid_for(m), BK, 0, s>>>(m, g->o2e, g->osup, g->esup);
-        TC_LAUNCHED();
-    }
+    TC_TRY(support_to_edge_order(g, s));
     uint32_t hch = 0;
     TC_HIP(hipMemcpyAsync(&hch, tot, 4, hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));

@@ -102,6 +102,10 @@ tc_status tc_sort_u64(uint64_t **keys, uint64_t **tmp_keys, int64_t n, int bits,
 tc_status tc_sort_u32_index(const uint32_t *src, uint32_t **keys, uint32_t **vals,
                             uint32_t **tmp_keys, uint32_t **tmp_vals, int64_t n, int bits,
                             hipStream_t s);
+// One stable pass: the (key, value) pairs ordered by the 8-bit digit
+// (key >> shift) & 255, written to keys_out / vals_out (inputs unchanged).
+tc_status tc_partition_u32_u32(const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out,
+                               uint32_t *vals_out, int64_t n, int shift, hipStream_t s);
 // the same with 64-bit values (hi[i] << 32) | i
 tc_status tc_sort_u32_index_hi(const uint32_t *src, const uint32_t *hi, uint32_t **keys,
                                uint64_t **vals, uint32_t **tmp_keys, uint64_t **tmp_vals,

@@ -281,6 +281,24 @@ tc_status tc_sort_u64_u32(uint64_t **keys, uint32_t **vals, uint64_t **tmp_keys,
     return radix_sort<uint64_t, uint32_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s);
 }
 
+tc_status tc_partition_u32_u32(const uint32_t *keys, const uint32_t *vals, uint32_t *keys_out,
+                               uint32_t *vals_out, int64_t n, int shift, hipStream_t s) {
+    if (n < 0 || shift < 0 || shift > 24) return TC_ERR_INVALID_ARG;
+    if (n == 0) return TC_OK;
+    if (n >= (int64_t)0xFFFFFFFFll) return TC_ERR_UNSUPPORTED;
+    constexpr int ITEMS = sort_items<uint32_t, uint32_t, true>();
+    const bool big = n >= SORT_BIG_TILES_MIN;
+    const int64_t tiles = tc_div_up(n, (int64_t)SORT_BLOCK * (big ? ITEMS : SORT_SMALL_ITEMS));
+    tc_scratch tmp(s);
+    uint32_t *counts = nullptr;
+    TC_TRY(tmp.get(&counts, tiles * RADIX));
+    if (big)
+        return radix_pass<uint32_t, uint32_t, true, ITEMS>(keys, vals, keys_out, vals_out, n, shift,
+                                                           counts, tiles, nullptr, s);
+    return radix_pass<uint32_t, uint32_t, true, SORT_SMALL_ITEMS>(keys, vals, keys_out, vals_out, n,
+                                                                  shift, counts, tiles, nullptr, s);
+}
+
 tc_status tc_sort_u32_u32(uint32_t **keys, uint32_t **vals, uint32_t **tmp_keys,
                           uint32_t **tmp_vals, int64_t n, int bits, hipStream_t s) {
     return radix_sort<uint32_t, uint32_t, true>(keys, vals, tmp_keys, tmp_vals, n, bits, s);
