@@ -163,6 +163,29 @@ __device__ __forceinline__ void bitmap_find_n(const BitmapRow &b, const uint32_t
     }
 }
 
+// The same probe, as a counter index that is always in bounds and a hit bit:
+// q = entries of the row before the key's place (spare, this lane's spare
+// counter, for a key outside the span), hit = 1 if the key is in the row.
+template <int N>
+__device__ __forceinline__ void bitmap_probe_n(const BitmapRow &b, const uint32_t (&key)[N],
+                                               int spare, int (&q)[N], uint32_t (&hit)[N]) {
+    uint32_t idx[N];
+    uint2 w[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        idx[e] = key[e] - b.lo;  // keys below lo wrap above span
+        w[e] = b.bm[idx[e] < b.span ? idx[e] >> 5 : 0];
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const uint32_t sh = idx[e] & 31;
+        const uint32_t in = idx[e] < b.span ? 1u : 0u;
+        hit[e] = ((w[e].x >> sh) & 1u) & in;
+        const int pos = (int)(w[e].y + (uint32_t)__popc(w[e].x & ((1u << sh) - 1u)));
+        q[e] = in ? pos : spare;
+    }
+}
+
 // Builds the bitmap of row ocol[vstart, vstart + d) (sorted ranks) with the
 // threads of a workgroup; words beyond the span are not touched.
 __device__ void bitmap_build(uint2 *bm, uint32_t *scan, const int32_t *__restrict__ ocol,
@@ -274,7 +297,17 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                     for (int e = 0; e < 8; ++e)
                         qc[e] = kk[e] <= hmax ? row_search(ocol, vstart, dv, kk[e]) : -1;
                 } else if constexpr (LK == LK_BITMAP) {
-                    bitmap_find_n<8>(bmr, kk, qc);
+                    // the counter index is always valid (the key's place in
+                    // the row, or this lane's spare counter outside the
+                    // span), and the add is the hit bit itself
+                    uint32_t hb[8];
+                    bitmap_probe_n<8>(bmr, kk, dv + lane, qc, hb);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        mask |= hb[e] << (c + e);
+                        atomicAdd(&lsup[qc[e]], hb[e]);
+                    }
+                    continue;
                 } else {
                     table_find_n<8>(t, kk, hmax, qc);
                 }
