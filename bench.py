@@ -118,7 +118,20 @@ def cpu_baseline(src, dst, n, m, stride):
                    f"v with v % {stride} == 0 ({count:.1f} s, scaled x{stride}); "
                    f"wall {wall:.1f} s"),
         "est_full_s": full,
+        "cpu_model": host_cpu_model(),
     }
+
+
+def host_cpu_model():
+    """The host CPU's model name, from /proc/cpuinfo (None if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def batched_leg(args, stream, autotune):
@@ -556,7 +569,8 @@ def main():
         stride = args.cpu_stride or max(1, 1 << max(0, args.scale - 20))
         log(f"CPU baseline: oracle O2 with row stride {stride}")
         cb = cpu_baseline(src, dst, n, m, stride)
-        result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                      "cpu_model")}
         log(f"CPU baseline done: {cb['value']:.3e} edges/s, est. full {cb['est_full_s']:.1f} s")
     if args.copy_calibration > 0:
         nbytes = int(args.copy_calibration * (1 << 30))

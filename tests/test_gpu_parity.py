@@ -136,6 +136,33 @@ def test_every_schedule_gives_identical_bytes(tclib, ti):
     assert_parity(run_gpu(tclib, src, dst, n, tuning=TUNINGS[ti]), ref)
 
 
+@pytest.mark.parametrize("algo", [1, 2])
+def test_every_bin_runs(tclib, algo):
+    # with an LDS limit of 1024 entries the clique's rows (699 higher
+    # neighbours) are looked up in device memory; the work statistics show
+    # that light, heavy and huge rows all ran, and the result is exact
+    src, dst, n = gg.rmat(13, 16, seed=9)
+    ks, kd, kn = gg.clique(700)
+    src = np.concatenate([src, ks + n]).astype(np.int32)
+    dst = np.concatenate([dst, kd + n]).astype(np.int32)
+    n = n + kn
+    ref = native.o1_definition(src, dst, n)
+    tuning = {"algorithm": algo, "lds_max_entries": 1024, "light_max_dplus": 16}
+    _say("bins, algorithm", algo)
+    g = tclib.Graph.from_edges(torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), n)
+    st = g.compute(tuning)
+    ws = g.work_stats()
+    res = g.results()
+    res["eu"], res["ev"] = g.edges()
+    res["status"] = st
+    res["m"] = g.m
+    g.close()
+    assert ws["algorithm"] == algo
+    for b in ("light", "heavy", "huge"):
+        assert ws["rows_" + b] > 0 and ws["cand_" + b] > 0, b
+    assert_parity(res, ref)
+
+
 def test_rmat_s20_full_parity(tclib):
     src, dst, n = gg.rmat(20, 16, seed=20)
     _say("R-MAT s20 oracle")
