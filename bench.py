@@ -487,13 +487,16 @@ def main():
     log("stage ms", json.dumps({k: round(v, 3) for k, v in stages.items()}))
     log("work", json.dumps(work))
 
-    # Roofline of the dominant kernel: algorithmic bytes per launch = 4 B per
-    # streamed candidate (Σ_{v→u} |N_H(u)| over the kernel's rows) + 4 B to
-    # read and 4 B to update each of its rows' own slots + 8 B per row offset.
+    # Roofline of the dominant kernel: algorithmic bytes per launch = the
+    # streamed candidates (4 B each, 2 B for those read as 16-bit entries:
+    # pivots among the top 2^16 ranks) + 8 B per scanned pair (its in-pair
+    # word) + 8 B per pivot row (row offsets).
     bins = {"count_light": "light", "count_heavy": "heavy", "count_huge": "huge"}
     dom = max(bins, key=lambda k: stages[k])
     b = bins[dom]
-    algo_bytes = 4 * work[f"cand_{b}"] + 8 * work[f"edges_{b}"] + 8 * work[f"rows_{b}"]
+    c16 = work.get(f"cand_{b}_16", 0)
+    algo_bytes = (4 * (work[f"cand_{b}"] - c16) + 2 * c16 + 8 * work[f"edges_{b}"]
+                  + 8 * work[f"rows_{b}"])
     dur_s = stages[dom] / 1e3
     achieved = algo_bytes / dur_s / 1e9 if dur_s > 0 else 0.0
     digest = source_digest(["tc_count.hip", "tc_count_mid.hip", "tc_table.h", "tc_internal.h"])

@@ -232,8 +232,11 @@ tc_status tc_numerator_algebraic(const tc_graph *g, uint64_t *num, int32_t mem_k
 tc_status tc_graph_device_bytes(const tc_graph *g, int64_t *bytes);
 
 /* Estimate of the peak device bytes tc_graph_from_edges + tc_compute need
- * for num_pairs pairs over n vertices (an upper bound), for admission
- * control by callers with a memory budget. */
+ * for num_pairs pairs over n vertices, for admission control by callers
+ * with a memory budget.  It bounds the peak while the middle pivot's bit
+ * matrices (Σ_v C(d+(v), 2) / 8 bytes over the oriented rows) stay within
+ * about 20 bytes per pair, as on sparse graphs (R-MAT scale 24: 20 bytes
+ * per pair); denser graphs, e.g. large cliques, need that much more. */
 int64_t tc_estimate_device_bytes(int64_t num_pairs, int32_t n);
 
 /* Releases the handle and its device memory (NULL is a no-op).  Waits for
@@ -300,7 +303,11 @@ tc_status tc_top_k(const tc_graph *g, int32_t k, int32_t *vertices, double *valu
  *   Σ |{w ∈ N_H(u) : w > v}| over the pairs u ∈ N_L(v) of the bin's pivots
  *   v; the edge counts are the oriented edges (low pivot) or pairs (middle
  *   pivot) of each bin.  Merge work is Σ_{v→u} (|N_H(v)| + |N_H(u)|),
- *   wedges Σ_v C(|N_H(v)|, 2), W_hash Σ_{v→u} |N_H(u)|.
+ *   wedges Σ_v C(|N_H(v)|, 2), W_hash Σ_{v→u} |N_H(u)|.  The middle
+ *   pivot reads the candidates of pivots among the top 2^16 ranks as 16-bit
+ *   entries (rank less n - 2^16) in its wavefront and workgroup kernels;
+ *   TC_STAT_CAND_HEAVY_16 is the part of the heavy bin's candidates read so
+ *   (0 after the low pivot).
  * ---------------------------------------------------------------------- */
 #define TC_NUM_STAGES 10
 enum {
@@ -317,14 +324,14 @@ enum {
                                  the low pivot: + symmetric adjacency)   */
     TC_STAGE_AGGREGATE = 9    /* Algorithm 2 sums + quotient            */
 };
-#define TC_NUM_WORK_STATS 17
+#define TC_NUM_WORK_STATS 18
 enum {
     TC_STAT_N = 0, TC_STAT_M = 1, TC_STAT_MAX_DPLUS = 2,
     TC_STAT_ROWS_LIGHT = 3, TC_STAT_ROWS_HEAVY = 4, TC_STAT_ROWS_HUGE = 5,
     TC_STAT_CAND_LIGHT = 6, TC_STAT_CAND_HEAVY = 7, TC_STAT_CAND_HUGE = 8,
     TC_STAT_MERGE_WORK = 9, TC_STAT_WEDGES = 10, TC_STAT_TRIANGLES = 11,
     TC_STAT_EDGES_LIGHT = 12, TC_STAT_EDGES_HEAVY = 13, TC_STAT_EDGES_HUGE = 14,
-    TC_STAT_W_HASH = 15, TC_STAT_ALGORITHM = 16
+    TC_STAT_W_HASH = 15, TC_STAT_ALGORITHM = 16, TC_STAT_CAND_HEAVY_16 = 17
 };
 
 tc_status tc_set_profiling(int32_t on);

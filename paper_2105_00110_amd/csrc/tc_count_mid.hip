@@ -80,6 +80,22 @@ static inline unsigned grid_for(int64_t n, int block = BK) {
 // ---------------------------------------------------------------------------
 // Transposed orientation
 // ---------------------------------------------------------------------------
+// The 16-bit copy of ocol: two entries per thread, r - base for ranks at or
+// above base, 0 for the others and for the padding.
+__global__ void k_ocol16(int64_t pairs, int64_t m, const int32_t *__restrict__ ocol, int32_t base,
+                         uint32_t *__restrict__ o16) {
+    GRID_STRIDE(i, pairs) {
+        uint32_t h[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t k = 2 * i + e;
+            const int32_t r = k < m ? ocol[k] : 0;
+            h[e] = r >= base ? (uint32_t)(r - base) : 0u;
+        }
+        o16[i] = h[0] | h[1] << 16;
+    }
+}
+
 // Number of lower-ordered neighbours of rank r: its degree less d+(r).
 __global__ void k_in_len(int32_t n, const int32_t *__restrict__ perm,
                          const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ orp,
@@ -134,8 +150,15 @@ __global__ void k_item_write(int32_t n, const uint32_t *__restrict__ cnt,
 //              word x holds bits (rank - lo) in [32x, 32x + 32) and the
 //              number of row entries before them; a probe is one 8-byte
 //              read, a bit test and a popcount.
+//   LK_BITMAP16  for pivots v among the top 2^16 ranks, whose candidates
+//              are 16-bit entries: the bitmap starts at rank v + 1 and has
+//              2048 words, which hold every rank a candidate can have, and
+//              any 16-bit value indexes inside it.  Words past the row's
+//              last entry read as no bits, so a probe needs no range test;
+//              a miss adds 0 to the lane's spare counter.
 // ---------------------------------------------------------------------------
-constexpr int LK_HASH = 0, LK_GLOBAL = 1, LK_BITMAP = 2;
+constexpr int LK_HASH = 0, LK_GLOBAL = 1, LK_BITMAP = 2, LK_BITMAP16 = 3;
+constexpr int BITMAP16_WORDS = 2048;
 
 struct BitmapRow {
     const uint2 *bm;  // {bits, entries before this word}
@@ -186,6 +209,27 @@ __device__ __forceinline__ void bitmap_probe_n(const BitmapRow &b, const uint32_
     }
 }
 
+// The LK_BITMAP16 probe: q = entries of the row before the key's place (at
+// most the row length), hit = 1 if the key is in the row.  Keys are 16-bit
+// ranks less the base of b.lo's footing; the index wraps within 2^16.
+template <int N>
+__device__ __forceinline__ void bitmap16_probe_n(const BitmapRow &b, const uint32_t (&key)[N],
+                                                 int (&q)[N], uint32_t (&hit)[N]) {
+    uint32_t idx[N];
+    uint2 w[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        idx[e] = (key[e] - b.lo) & 0xFFFFu;
+        w[e] = b.bm[idx[e] >> 5];
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const uint32_t sh = idx[e] & 31;
+        hit[e] = (w[e].x >> sh) & 1u;
+        q[e] = (int)(w[e].y + (uint32_t)__popc(w[e].x & ((1u << sh) - 1u)));
+    }
+}
+
 // Builds the bitmap of row ocol[vstart, vstart + d) (sorted ranks) with the
 // threads of a workgroup; words beyond the span are not touched.
 __device__ void bitmap_build(uint2 *bm, uint32_t *scan, const int32_t *__restrict__ ocol,
@@ -223,9 +267,10 @@ __device__ void bitmap_build(uint2 *bm, uint32_t *scan, const int32_t *__restric
 // ---------------------------------------------------------------------------
 // GL lanes take the group (a whole wavefront for GL = 64, or one of its
 // 64 / GL groups, each with its own arrays and counters); at most GL pairs.
-template <int LK, int GL = TC_WAVE>
+template <int LK, int GL = TC_WAVE, bool N16 = false>
 __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                                           const int32_t *__restrict__ ocol,
+                                          const uint16_t *__restrict__ ocol16,
                                           const uint64_t *__restrict__ in_pair,
                                           const int64_t *__restrict__ rowbase, int64_t g0,
                                           int64_t gend, const RowTable &t, const BitmapRow &bmr,
@@ -235,6 +280,7 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                                           uint32_t *__restrict__ bits, uint32_t *__restrict__ osup,
                                           unsigned long long &found) {
     static_assert(GL <= TC_WAVE && TC_WAVE % GL == 0, "group width");
+    static_assert(LK != LK_BITMAP16 || N16, "the 2048-word bitmap takes 16-bit keys");
     const int lane = __lane_id() % GL;
     const int64_t i = g0 + lane;
     int64_t words = 0;
@@ -275,13 +321,37 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
             const int64_t kw = x - gx[p];
             const int64_t c0 = gs[p] + 32 * kw;
             const int cnt = min(32, gt[p] - 32 * (int)kw);
-            // whole 32-entry run (the array is padded past its end);
+            // whole 32-entry run (the arrays are padded past their end);
             // entries past the tail are masked to EMPTY
             uint32_t ww[32];
+            if constexpr (N16) {
+                // 17 aligned words hold the 32 entries from c0; an odd c0
+                // starts in the upper half of the first
+                const uint32_t *o32 = reinterpret_cast<const uint32_t *>(ocol16);
+                const int64_t q = c0 >> 1;
+                const uint32_t sh = (uint32_t)(c0 & 1) << 4;
+                uint32_t dw[17];
 #pragma unroll
-            for (int b = 0; b < 32; ++b) {
-                const uint32_t v = (uint32_t)ocol[c0 + b];
-                ww[b] = b < cnt ? v : EMPTY;
+                for (int j = 0; j < 17; ++j) dw[j] = o32[q + j];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const uint32_t a = __builtin_amdgcn_alignbit(dw[j + 1], dw[j], sh);
+                    if constexpr (LK == LK_BITMAP16) {
+                        // every value probes inside the bitmap: the hits of
+                        // entries past the tail are masked after the probe
+                        ww[2 * j] = a & 0xFFFFu;
+                        ww[2 * j + 1] = a >> 16;
+                    } else {
+                        ww[2 * j] = 2 * j < cnt ? (a & 0xFFFFu) : EMPTY;
+                        ww[2 * j + 1] = 2 * j + 1 < cnt ? (a >> 16) : EMPTY;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < 32; ++b) {
+                    const uint32_t v = (uint32_t)ocol[c0 + b];
+                    ww[b] = b < cnt ? v : EMPTY;
+                }
             }
             // probe in batches of 8 (EMPTY, past the tail, is above every
             // rank and is never looked up); apply each batch's hits at once
@@ -296,6 +366,19 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
 #pragma unroll
                     for (int e = 0; e < 8; ++e)
                         qc[e] = kk[e] <= hmax ? row_search(ocol, vstart, dv, kk[e]) : -1;
+                } else if constexpr (LK == LK_BITMAP16) {
+                    // entries past the tail keep no hit; a miss adds 0 to
+                    // this lane's spare counter, so lanes never share a
+                    // counter on misses
+                    uint32_t hb[8];
+                    bitmap16_probe_n<8>(bmr, kk, qc, hb);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        hb[e] = c + e < cnt ? hb[e] : 0u;
+                        mask |= hb[e] << (c + e);
+                        atomicAdd(&lsup[hb[e] ? qc[e] : dv + lane], hb[e]);
+                    }
+                    continue;
                 } else if constexpr (LK == LK_BITMAP) {
                     // the counter index is always valid (the key's place in
                     // the row, or this lane's spare counter outside the
@@ -349,6 +432,7 @@ __global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ o
                                                    const int32_t *__restrict__ item_v,
                                                    const uint32_t *__restrict__ item_first,
                                                    int64_t nitems, int dcap, int item_pairs,
+                                                   const uint16_t *__restrict__ ocol16, int32_t r16,
                                                    uint32_t *__restrict__ osup,
                                                    unsigned long long *__restrict__ tri_total) {
     extern __shared__ uint4 lds4[];
@@ -374,14 +458,26 @@ __global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ o
         const int64_t vstart = orp[v];
         const int d = (int)(orp[v + 1] - vstart);
         const RowTable t{keys, pos, bucket_bits(d)};
+        // pivots among the top 2^16 ranks scan 16-bit entries; their table
+        // holds ranks less r16 to match
+        const bool n16 = v >= r16;
+        const uint32_t rel = n16 ? (uint32_t)r16 : 0u;
         for (int j = lane; j < (4 << t.bb); j += TC_WAVE) keys[j] = EMPTY;
         for (int j = lane; j < d; j += TC_WAVE) lsup[j] = 0;
-        for (int j = lane; j < d; j += TC_WAVE) table_insert(t, (uint32_t)ocol[vstart + j], j);
-        const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
-        for (int64_t g0 = first; g0 < pend; g0 += TC_WAVE)
-            mid_group<LK_HASH>(orp, ocol, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t,
-                               BitmapRow{nullptr, 0, 0}, hmax, lsup, vstart, d, gx, gs, gb, gt,
-                               bits, osup, found);
+        for (int j = lane; j < d; j += TC_WAVE)
+            table_insert(t, (uint32_t)ocol[vstart + j] - rel, j);
+        const uint32_t hmax = (uint32_t)ocol[vstart + d - 1] - rel;
+        for (int64_t g0 = first; g0 < pend; g0 += TC_WAVE) {
+            if (n16)
+                mid_group<LK_HASH, TC_WAVE, true>(orp, ocol, ocol16, in_pair, rowbase, g0,
+                                                  min(g0 + TC_WAVE, pend), t,
+                                                  BitmapRow{nullptr, 0, 0}, hmax, lsup, vstart, d,
+                                                  gx, gs, gb, gt, bits, osup, found);
+            else
+                mid_group<LK_HASH>(orp, ocol, nullptr, in_pair, rowbase, g0,
+                                   min(g0 + TC_WAVE, pend), t, BitmapRow{nullptr, 0, 0}, hmax,
+                                   lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
+        }
         for (int j = lane; j < d; j += TC_WAVE) {
             const uint32_t c = lsup[j];
             if (c) atomicAdd(&osup[vstart + j], c);
@@ -447,7 +543,7 @@ __global__ __launch_bounds__(256, 4) void k_mid_groups(const int64_t *__restrict
         for (int j = lane; j < d; j += GL) table_insert(t, (uint32_t)ocol[vstart + j], j);
         const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
         for (int64_t g0 = first; g0 < pend; g0 += GL)
-            mid_group<LK_HASH, GL>(orp, ocol, in_pair, rowbase, g0, min(g0 + GL, pend), t,
+            mid_group<LK_HASH, GL>(orp, ocol, nullptr, in_pair, rowbase, g0, min(g0 + GL, pend), t,
                                    BitmapRow{nullptr, 0, 0}, hmax, lsup, vstart, d, gx, gs, gb, gt,
                                    bits, osup, found);
         for (int j = lane; j < d; j += GL) {
@@ -471,7 +567,9 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ item_v,
                                                     const uint32_t *__restrict__ item_first,
                                                     int64_t nitems, int dmax, int item_pairs,
-                                                    int bitmap_words, uint32_t *__restrict__ osup,
+                                                    int bitmap_words,
+                                                    const uint16_t *__restrict__ ocol16, int32_t r16,
+                                                    uint32_t *__restrict__ osup,
                                                     unsigned long long *__restrict__ tri_total) {
     extern __shared__ uint4 lds4[];
     const int wpb = blockDim.x / TC_WAVE;
@@ -508,24 +606,54 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
         const int d = (int)(orp[v + 1] - vstart);
         RowTable t{keys, pos, 0};
         BitmapRow bmr{bm, 0, 0};
+        // pivots among the top 2^16 ranks scan 16-bit entries (ranks less
+        // r16); the lookup structure takes keys on the same footing
+        const bool n16 = LK != LK_GLOBAL && v >= r16;
+        const uint32_t rel = n16 ? (uint32_t)r16 : 0u;
         if constexpr (LK == LK_HASH) {
             t.bb = bucket_bits(d);
             for (int j = threadIdx.x; j < (4 << t.bb); j += blockDim.x) keys[j] = EMPTY;
             for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
             __syncthreads();
             for (int j = threadIdx.x; j < d; j += blockDim.x)
-                table_insert(t, (uint32_t)ocol[vstart + j], j);
+                table_insert(t, (uint32_t)ocol[vstart + j] - rel, j);
             __syncthreads();
         } else if constexpr (LK == LK_BITMAP) {
-            bmr.lo = (uint32_t)ocol[vstart];
-            bmr.span = (uint32_t)ocol[vstart + d - 1] - bmr.lo + 1;
             for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
-            bitmap_build(bm, scan, ocol, vstart, d, bmr.lo, bmr.span);
+            if (n16 && bitmap_words >= BITMAP16_WORDS) {
+                // LK_BITMAP16: 2048 words from rank v + 1
+                bmr.span = 32u * BITMAP16_WORDS;
+                bitmap_build(bm, scan, ocol, vstart, d, (uint32_t)v + 1u, bmr.span);
+                bmr.lo = (uint32_t)v + 1u - rel;
+            } else {
+                const uint32_t lo = (uint32_t)ocol[vstart];
+                bmr.span = (uint32_t)ocol[vstart + d - 1] - lo + 1;
+                bitmap_build(bm, scan, ocol, vstart, d, lo, bmr.span);
+                bmr.lo = lo - rel;
+            }
         }
-        const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
-        for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE)
-            mid_group<LK>(orp, ocol, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t, bmr, hmax,
-                          lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
+        const uint32_t hmax = (uint32_t)ocol[vstart + d - 1] - rel;
+        for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE) {
+            if constexpr (LK == LK_BITMAP) {
+                if (n16 && bitmap_words >= BITMAP16_WORDS) {
+                    mid_group<LK_BITMAP16, TC_WAVE, true>(orp, ocol, ocol16, in_pair, rowbase, g0,
+                                                          min(g0 + TC_WAVE, pend), t, bmr, hmax,
+                                                          lsup, vstart, d, gx, gs, gb, gt, bits,
+                                                          osup, found);
+                    continue;
+                }
+            }
+            if constexpr (LK != LK_GLOBAL) {
+                if (n16) {
+                    mid_group<LK, TC_WAVE, true>(orp, ocol, ocol16, in_pair, rowbase, g0,
+                                                 min(g0 + TC_WAVE, pend), t, bmr, hmax, lsup,
+                                                 vstart, d, gx, gs, gb, gt, bits, osup, found);
+                    continue;
+                }
+            }
+            mid_group<LK>(orp, ocol, nullptr, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t,
+                          bmr, hmax, lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
+        }
         if constexpr (LK != LK_GLOBAL) {
             __syncthreads();
             for (int j = threadIdx.x; j < d; j += blockDim.x) {
@@ -863,8 +991,10 @@ __global__ void k_row_words(int32_t n, const int64_t *__restrict__ orp, int64_t 
 // the pivot's |N_H|.
 __global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
                             const int32_t *__restrict__ ocol, const uint64_t *__restrict__ in_pair,
-                            int light_max, int huge_min, unsigned long long *__restrict__ acc) {
-    unsigned long long sums[6] = {0, 0, 0, 0, 0, 0};  // cand per bin, pairs per bin
+                            int light_max, int huge_min, int32_t r16,
+                            unsigned long long *__restrict__ acc) {
+    // cand per bin, pairs per bin, heavy cand read as 16-bit entries
+    unsigned long long sums[7] = {0, 0, 0, 0, 0, 0, 0};
     GRID_STRIDE(i, m) {
         const uint64_t pr = in_pair[i];
         const uint32_t k = (uint32_t)pr;
@@ -876,11 +1006,12 @@ __global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
         const int bin = d <= light_max ? 0 : (d < huge_min ? 1 : 2);
         sums[bin] += (unsigned long long)len;
         sums[3 + bin] += 1ull;
+        if (bin == 1 && v >= r16) sums[6] += (unsigned long long)len;
     }
 #pragma unroll
-    for (int b = 0; b < 6; ++b) {
+    for (int b = 0; b < 7; ++b) {
         const unsigned long long v = tc_wave_sum(sums[b]);
-        if (__lane_id() == 0 && v) atomicAdd(&acc[b < 3 ? 3 + b : 5 + b], v);
+        if (__lane_id() == 0 && v) atomicAdd(&acc[b < 3 ? 3 + b : (b < 6 ? 5 + b : 12)], v);
     }
 }
 
@@ -1003,9 +1134,24 @@ static tc_status bit_rows_prepare(tc_graph *g, hipStream_t s) {
     return TC_OK;
 }
 
+// The 16-bit copy of ocol for the pivots among the top 2^16 ranks (once per
+// handle): every entry after such a pivot in a row is a rank in
+// [rank16_base, n), below 2^16 once rank16_base is taken off.
+static tc_status ocol16_prepare(tc_graph *g, hipStream_t s) {
+    if (g->ocol16) return TC_OK;
+    g->rank16_base = g->n > 65536 ? g->n - 65536 : 0;
+    const int64_t total = (g->m + TC_OCOL_PAD + 1) & ~(int64_t)1;
+    TC_TRY(tc_graph_alloc(g, &g->ocol16, total, s));
+    k_ocol16<<<grid_for(total / 2), BK, 0, s>>>(total / 2, g->m, g->ocol, g->rank16_base,
+                                               reinterpret_cast<uint32_t *>(g->ocol16));
+    TC_LAUNCHED();
+    return TC_OK;
+}
+
 tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_entries,
                        unsigned long long *found, hipStream_t s) {
     TC_TRY(tc_mid_prepare(g, s));
+    TC_TRY(ocol16_prepare(g, s));
     const int light_max = t.light_max_dplus;
     int huge_min = max_entries / 2 + 1;
     if (huge_min <= light_max) huge_min = light_max + 1;
@@ -1095,7 +1241,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         if (blocks > 262144) blocks = 262144;
         k_mid_wave<<<(unsigned)blocks, wpb * TC_WAVE, (size_t)wpb * per_wave, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, wv_v, wv_f, n_wave,
-            light_max, wave_pairs, g->osup, found);
+            light_max, wave_pairs, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     if (n_lbitmap > 0) {
@@ -1103,7 +1249,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_lbitmap < 1048576 ? n_lbitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, lb_v, lb_f, n_lbitmap,
-            light_max, block_pairs, bw, g->osup, found);
+            light_max, block_pairs, bw, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 6, s);
@@ -1113,7 +1259,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_bitmap < 1048576 ? n_bitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bm_v, bm_f, n_bitmap,
-            hmax, block_pairs, bw, g->osup, found);
+            hmax, block_pairs, bw, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     if (n_block > 0) {
@@ -1122,7 +1268,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_block < 1048576 ? n_block : 1048576;
         k_mid_block<LK_HASH><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bl_v, bl_f, n_block, hmax,
-            block_pairs, 0, g->osup, found);
+            block_pairs, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 7, s);
@@ -1131,7 +1277,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_huge < 1048576 ? n_huge : 1048576;
         k_mid_block<LK_GLOBAL><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, hu_v, hu_f, n_huge, 0,
-            block_pairs, 0, g->osup, found);
+            block_pairs, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 8, s);
@@ -1177,8 +1323,9 @@ tc_status tc_mid_stats(tc_graph *g, unsigned long long *acc, hipStream_t s) {
     TC_TRY(tc_mid_prepare(g, s));
     const int light_max = g->light_max > 0 ? g->light_max : 64;
     const int huge_min = g->huge_min > 0 ? g->huge_min : 0x7FFFFFFF;
+    const int32_t r16 = g->n > 65536 ? g->n - 65536 : 0;  // as the count's 16-bit copy
     k_mid_stats<<<grid_for(g->m), BK, 0, s>>>(g->m, g->orp, g->ocol, g->in_pair, light_max,
-                                             huge_min, acc);
+                                             huge_min, r16, acc);
     TC_LAUNCHED();
     k_mid_pivots<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, g->in_ptr, light_max, huge_min, acc);
     TC_LAUNCHED();

@@ -146,6 +146,10 @@ struct tc_graph {
     // oriented CSR over ranks: row r holds the ranks above r, ascending
     int64_t *orp = nullptr;                         // [n+1]
     int32_t *ocol = nullptr;                        // [m]
+    // ocol for the pivots among the top 2^16 ranks: entries at or above
+    // rank16_base, less rank16_base (16 bits); other entries read 0
+    uint16_t *ocol16 = nullptr;                     // [m + TC_OCOL_PAD, rounded up to even]
+    int32_t rank16_base = 0;
     uint32_t *o2e = nullptr;                        // [m] canonical edge of each oriented slot
     int32_t *orow = nullptr;                        // [m] row (rank) of each oriented slot
     // transposed orientation (middle-pivot counting): pairs grouped by the

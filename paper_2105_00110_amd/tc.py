@@ -94,7 +94,7 @@ STAGES = ["csr_build", "degree_rank", "orient", "bin", "count_light", "count_hea
           "count_huge", "fold", "tri", "aggregate"]
 WORK_STATS = ["n", "m", "max_dplus", "rows_light", "rows_heavy", "rows_huge", "cand_light",
               "cand_heavy", "cand_huge", "merge_work", "wedges", "triangles", "edges_light",
-              "edges_heavy", "edges_huge", "w_hash", "algorithm"]
+              "edges_heavy", "edges_huge", "w_hash", "algorithm", "cand_heavy_16"]
 
 
 def load(path=None):
