@@ -209,24 +209,29 @@ __device__ __forceinline__ void bitmap_probe_n(const BitmapRow &b, const uint32_
     }
 }
 
-// The LK_BITMAP16 probe: q = entries of the row before the key's place (at
-// most the row length), hit = 1 if the key is in the row.  Keys are 16-bit
-// ranks less the base of b.lo's footing; the index wraps within 2^16.
+// The LK_BITMAP16 probe of the entries k0 .. k0 + N - 1 of a lane's run, of
+// which the first cnt - k0 lie in the tail: hit = 1 if the entry is in the
+// tail and in the row, q = the key's place in the row for a hit, else
+// spare.  Keys are 16-bit ranks on b.lo's footing; the index wraps within
+// 2^16, and the bit-field reads take their offset and width from the low 5
+// bits of d.
 template <int N>
 __device__ __forceinline__ void bitmap16_probe_n(const BitmapRow &b, const uint32_t (&key)[N],
-                                                 int (&q)[N], uint32_t (&hit)[N]) {
-    uint32_t idx[N];
+                                                 int k0, int cnt, int spare, int (&q)[N],
+                                                 uint32_t (&hit)[N]) {
+    uint32_t dd[N];
     uint2 w[N];
 #pragma unroll
     for (int e = 0; e < N; ++e) {
-        idx[e] = (key[e] - b.lo) & 0xFFFFu;
-        w[e] = b.bm[idx[e] >> 5];
+        dd[e] = key[e] - b.lo;
+        w[e] = b.bm[__builtin_amdgcn_ubfe(dd[e], 5u, 11u)];
     }
 #pragma unroll
     for (int e = 0; e < N; ++e) {
-        const uint32_t sh = idx[e] & 31;
-        hit[e] = (w[e].x >> sh) & 1u;
-        q[e] = (int)(w[e].y + (uint32_t)__popc(w[e].x & ((1u << sh) - 1u)));
+        const bool h = __builtin_amdgcn_ubfe(w[e].x, dd[e], 1u) != 0u && k0 + e < cnt;
+        const uint32_t pos = w[e].y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w[e].x, 0u, dd[e]));
+        hit[e] = h ? 1u : 0u;
+        q[e] = h ? (int)pos : spare;
     }
 }
 
@@ -371,12 +376,11 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
                     // this lane's spare counter, so lanes never share a
                     // counter on misses
                     uint32_t hb[8];
-                    bitmap16_probe_n<8>(bmr, kk, qc, hb);
+                    bitmap16_probe_n<8>(bmr, kk, c, cnt, dv + lane, qc, hb);
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        hb[e] = c + e < cnt ? hb[e] : 0u;
                         mask |= hb[e] << (c + e);
-                        atomicAdd(&lsup[hb[e] ? qc[e] : dv + lane], hb[e]);
+                        atomicAdd(&lsup[qc[e]], hb[e]);
                     }
                     continue;
                 } else if constexpr (LK == LK_BITMAP) {
@@ -556,7 +560,11 @@ __global__ __launch_bounds__(256, 4) void k_mid_groups(const int64_t *__restrict
 }
 
 // One workgroup per item; its wavefronts share the pivot's lookup structure
-// and take the item's 64-pair groups in turn.
+// and take the item's 64-pair groups in turn.  With wide16 (the workgroup
+// pivots' launch) pivots among the top 2^16 ranks use LK_BITMAP16 when the
+// bitmap has room for its 2048 words; short items (the wavefront pivots
+// moved here) keep the bitmap over their row's span, which is cheaper to
+// build.
 template <int LK>
 __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ orp,
                                                     const int32_t *__restrict__ ocol,
@@ -567,7 +575,7 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ item_v,
                                                     const uint32_t *__restrict__ item_first,
                                                     int64_t nitems, int dmax, int item_pairs,
-                                                    int bitmap_words,
+                                                    int bitmap_words, int wide16,
                                                     const uint16_t *__restrict__ ocol16, int32_t r16,
                                                     uint32_t *__restrict__ osup,
                                                     unsigned long long *__restrict__ tri_total) {
@@ -620,7 +628,7 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
             __syncthreads();
         } else if constexpr (LK == LK_BITMAP) {
             for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
-            if (n16 && bitmap_words >= BITMAP16_WORDS) {
+            if (n16 && wide16 && bitmap_words >= BITMAP16_WORDS) {
                 // LK_BITMAP16: 2048 words from rank v + 1
                 bmr.span = 32u * BITMAP16_WORDS;
                 bitmap_build(bm, scan, ocol, vstart, d, (uint32_t)v + 1u, bmr.span);
@@ -635,7 +643,7 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
         const uint32_t hmax = (uint32_t)ocol[vstart + d - 1] - rel;
         for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE) {
             if constexpr (LK == LK_BITMAP) {
-                if (n16 && bitmap_words >= BITMAP16_WORDS) {
+                if (n16 && wide16 && bitmap_words >= BITMAP16_WORDS) {
                     mid_group<LK_BITMAP16, TC_WAVE, true>(orp, ocol, ocol16, in_pair, rowbase, g0,
                                                           min(g0 + TC_WAVE, pend), t, bmr, hmax,
                                                           lsup, vstart, d, gx, gs, gb, gt, bits,
@@ -1249,7 +1257,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_lbitmap < 1048576 ? n_lbitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, lb_v, lb_f, n_lbitmap,
-            light_max, block_pairs, bw, g->ocol16, g->rank16_base, g->osup, found);
+            light_max, block_pairs, bw, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 6, s);
@@ -1259,7 +1267,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_bitmap < 1048576 ? n_bitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bm_v, bm_f, n_bitmap,
-            hmax, block_pairs, bw, g->ocol16, g->rank16_base, g->osup, found);
+            hmax, block_pairs, bw, 1, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     if (n_block > 0) {
@@ -1268,7 +1276,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_block < 1048576 ? n_block : 1048576;
         k_mid_block<LK_HASH><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bl_v, bl_f, n_block, hmax,
-            block_pairs, 0, g->ocol16, g->rank16_base, g->osup, found);
+            block_pairs, 0, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 7, s);
@@ -1277,7 +1285,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_huge < 1048576 ? n_huge : 1048576;
         k_mid_block<LK_GLOBAL><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, hu_v, hu_f, n_huge, 0,
-            block_pairs, 0, g->ocol16, g->rank16_base, g->osup, found);
+            block_pairs, 0, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 8, s);
