@@ -82,9 +82,9 @@ def source_digest(names):
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel_key, digest):
-    """HBM bytes per dispatch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+def counter_entry(kernel_key, digest):
+    """The committed rocprofv3 counter summary of a kernel, if it was taken
+    on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "counters_rmat_s24.json")
     try:
         with open(path) as f:
@@ -94,7 +94,7 @@ def counter_traffic(kernel_key, digest):
     k = d.get("kernels", {}).get(kernel_key)
     if not k or d.get("source_digest") != digest:
         return None
-    return k.get("hbm_bytes_per_dispatch")
+    return k
 
 
 def cpu_baseline(src, dst, n, m, stride):
@@ -500,7 +500,7 @@ def main():
     dur_s = stages[dom] / 1e3
     achieved = algo_bytes / dur_s / 1e9 if dur_s > 0 else 0.0
     digest = source_digest(["tc_count.hip", "tc_count_mid.hip", "tc_table.h", "tc_internal.h"])
-    traffic = counter_traffic(dom, digest)
+    counters = counter_entry(dom, digest) or {}
     kernel_names = {"count_light": "k_mid_wave", "count_heavy": "k_mid_block",
                     "count_huge": "k_mid_block<true>"}
     if work.get("algorithm") == 1:
@@ -514,9 +514,12 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
+        "traffic": counters.get("hbm_bytes_per_dispatch"),
         "algorithmic_bytes": int(algo_bytes),
         "avg_ms": round(stages[dom], 3),
+        # fraction of cycles the SIMDs issued vector ALU work, from the same
+        # counter summary (null when it is stale)
+        "valu_busy": counters.get("valu_busy"),
     }
 
     result = {
