@@ -28,6 +28,7 @@ against the plain one-graph-per-launch form on the same GPU:
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -75,10 +76,17 @@ def parse():
 
 
 def source_digest(names):
+    """Digest of the code of the given sources: comments, blank lines and
+    indentation do not count, so a counter summary stays valid across
+    edits that change no code."""
     h = hashlib.sha256()
     for n in names:
-        with open(os.path.join(ROOT, "paper_2105_00110_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2105_00110_amd", "csrc", n)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.strip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

@@ -27,6 +27,12 @@
 // holds ceil((d-1-i)/32) words (d = |N_H(u)|), so row i starts at word
 // S(d) - S(d-i) with S(d) = Σ_{t<d} ceil(t/32).
 //
+// 16-bit candidates.  Every entry scanned for a pivot v is a rank above v,
+// so for the pivots among the top 2^16 ranks it fits in 16 bits once
+// n - 2^16 is taken off.  Those pivots scan ocol16, a 16-bit copy of ocol,
+// and key their lookup structure the same way: half the bytes of the scan
+// for most of its candidates on skewed graphs.
+//
 // Work mapping.  A work item is a pivot with a slice of its pairs.  A
 // wavefront takes 64 pairs at a time and flattens their bit rows: a prefix
 // sum of the row lengths in words places word x of the group, and the lane
@@ -78,10 +84,9 @@ static inline unsigned grid_for(int64_t n, int block = BK) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 // ---------------------------------------------------------------------------
-// Transposed orientation
-// ---------------------------------------------------------------------------
-// The 16-bit copy of ocol: two entries per thread, r - base for ranks at or
+// 16-bit copy of ocol: two entries per thread, r - base for ranks at or
 // above base, 0 for the others and for the padding.
+// ---------------------------------------------------------------------------
 __global__ void k_ocol16(int64_t pairs, int64_t m, const int32_t *__restrict__ ocol, int32_t base,
                          uint32_t *__restrict__ o16) {
     GRID_STRIDE(i, pairs) {
@@ -96,6 +101,9 @@ __global__ void k_ocol16(int64_t pairs, int64_t m, const int32_t *__restrict__ o
     }
 }
 
+// ---------------------------------------------------------------------------
+// Transposed orientation
+// ---------------------------------------------------------------------------
 // Number of lower-ordered neighbours of rank r: its degree less d+(r).
 __global__ void k_in_len(int32_t n, const int32_t *__restrict__ perm,
                          const int64_t *__restrict__ row_ptr, const int64_t *__restrict__ orp,
