@@ -392,6 +392,9 @@ namespace {
 __global__ void k_work_stats(int32_t n, const int64_t *__restrict__ orp,
                              const int32_t *__restrict__ ocol, int light_max, int huge_min,
                              bool low_bins, unsigned long long *__restrict__ acc) {
+    // per-thread sums of the 12 words, added once per wavefront: the words
+    // are shared by every row
+    unsigned long long sums[12] = {};
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = orp[r], e = orp[r + 1];
@@ -404,15 +407,23 @@ __global__ void k_work_stats(int32_t n, const int64_t *__restrict__ orp,
             cand += du;
             merge += d + du;
         }
-        int bin = d < 2 ? -1 : (d <= light_max ? 0 : (d < huge_min ? 1 : 2));
-        if (bin >= 0 && low_bins) {
-            atomicAdd(&acc[bin], 1ull);
-            atomicAdd(&acc[3 + bin], cand);
-            atomicAdd(&acc[8 + bin], (unsigned long long)d);
+        const int bin = d < 2 ? -1 : (d <= light_max ? 0 : (d < huge_min ? 1 : 2));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (bin == q && low_bins) {
+                sums[q] += 1ull;
+                sums[3 + q] += cand;
+                sums[8 + q] += (unsigned long long)d;
+            }
         }
-        atomicAdd(&acc[6], merge);
-        atomicAdd(&acc[7], (unsigned long long)(d * (d - 1) / 2));
-        atomicAdd(&acc[11], cand);
+        sums[6] += merge;
+        sums[7] += (unsigned long long)(d * (d - 1) / 2);
+        sums[11] += cand;
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const unsigned long long t = tc_wave_sum(sums[q]);
+        if (__lane_id() == 0 && t) atomicAdd(&acc[q], t);
     }
 }
 
@@ -431,7 +442,8 @@ tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s) {
     int light_max = g->light_max > 0 ? g->light_max : 64;
     int huge_min = g->huge_min > 0 ? g->huge_min : 0x7FFFFFFF;
     const bool mid = g->algo_used != TC_ALGO_LOW_PIVOT;
-    k_work_stats<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, g->ocol, light_max, huge_min, !mid,
+    const unsigned wg = grid_for(g->n) < 4096u ? grid_for(g->n) : 4096u;
+    k_work_stats<<<wg, BK, 0, s>>>(g->n, g->orp, g->ocol, light_max, huge_min, !mid,
                                                acc);
     TC_LAUNCHED();
     if (mid) TC_TRY(tc_mid_stats(g, acc, s));

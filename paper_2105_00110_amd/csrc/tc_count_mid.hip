@@ -1340,10 +1340,13 @@ tc_status tc_mid_stats(tc_graph *g, unsigned long long *acc, hipStream_t s) {
     const int light_max = g->light_max > 0 ? g->light_max : 64;
     const int huge_min = g->huge_min > 0 ? g->huge_min : 0x7FFFFFFF;
     const int32_t r16 = g->n > 65536 ? g->n - 65536 : 0;  // as the count's 16-bit copy
-    k_mid_stats<<<grid_for(g->m), BK, 0, s>>>(g->m, g->orp, g->ocol, g->in_pair, light_max,
+    // a bounded grid: each wavefront adds its sums to the same few words
+    const unsigned sg = grid_for(g->m) < 4096u ? grid_for(g->m) : 4096u;
+    k_mid_stats<<<sg, BK, 0, s>>>(g->m, g->orp, g->ocol, g->in_pair, light_max,
                                              huge_min, r16, acc);
     TC_LAUNCHED();
-    k_mid_pivots<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, g->in_ptr, light_max, huge_min, acc);
+    const unsigned pg = grid_for(g->n) < 4096u ? grid_for(g->n) : 4096u;
+    k_mid_pivots<<<pg, BK, 0, s>>>(g->n, g->orp, g->in_ptr, light_max, huge_min, acc);
     TC_LAUNCHED();
     return TC_OK;
 }
