@@ -395,8 +395,9 @@ def resident_run(reqs, cfg, capacity):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the sharded "
-              f"design is described in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the library "
+              f"runs one graph or batch per GPU, and a sharded path is not built",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -557,7 +558,7 @@ def main():
         "roofline": roofline,
         # the count priced in the low-pivot form, 4 B per candidate of
         # W_hash = sum over v->u of |N_H(u)|, over the whole count stage
-        "survey_algorithmic_count": {
+        "hash_form_algorithmic_count": {
             "bytes": 4 * work["w_hash"], "ms": round(count_ms, 3),
             "GBps": round(4 * work["w_hash"] / (count_ms / 1e3) / 1e9, 1),
             "frac_of_peak": round(4 * work["w_hash"] / (count_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
