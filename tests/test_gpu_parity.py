@@ -163,6 +163,34 @@ def test_every_bin_runs(tclib, algo):
     assert_parity(res, ref)
 
 
+@pytest.mark.parametrize("n", [65536, 65537, 70000])
+def test_sixteen_bit_candidates_at_the_base(tclib, n):
+    # the middle pivot reads the candidates of pivots among the top 2^16
+    # ranks as 16-bit entries: at n = 2^16 every pivot does, at 2^16 + 1 all
+    # but rank 0, at 70000 the lowest 4464 ranks do not (BA: every vertex
+    # has degree >= 8, so ranks span all of n)
+    src, dst, n_ba = gg.ba(n, 8, seed=n)
+    assert n_ba == n
+    ref = native.o1_definition(src, dst, n)
+    for tuning in ({"algorithm": 2}, {"algorithm": 2, "light_max_dplus": 16}):
+        _say("16-bit base, n", n, "tuning", tuning)
+        assert_parity(run_gpu(tclib, src, dst, n, tuning=tuning), ref)
+
+
+def test_sixteen_bit_candidates_both_sides_in_one_launch(tclib):
+    # ER at average degree 64 over 70000 vertices: even the lowest ranks
+    # have rows of about 50 entries, so with light rows of at most 16
+    # entries the workgroup launch holds pivots below and above the 16-bit
+    # base, under the bitmap and under the hash
+    n = 70000
+    src, dst, _ = gg.er(n, 64.0 / n, seed=7)
+    ref = native.o1_definition(src, dst, n)
+    for tuning in ({"algorithm": 2, "light_max_dplus": 16},
+                   {"algorithm": 2, "light_max_dplus": 16, "bitmap_words": 0}):
+        _say("16-bit base, ER 70000, tuning", tuning)
+        assert_parity(run_gpu(tclib, src, dst, n, tuning=tuning), ref)
+
+
 def test_rmat_s20_full_parity(tclib):
     src, dst, n = gg.rmat(20, 16, seed=20)
     _say("R-MAT s20 oracle")
