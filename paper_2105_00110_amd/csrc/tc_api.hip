@@ -222,7 +222,7 @@ void free_graph_arrays(tc_graph *g, hipStream_t s) {
                     g->orp,  g->ocol, g->o2e,     g->osup, g->esup,  g->flag, g->tri,
                     g->num,  g->tcv,  g->triG,    g->vtx_off, g->err, g->bin_rows,
                     g->in_ptr, g->in_pair, g->rowbase, g->hitbits, g->orow,
-                    g->run_us, g->lt_key, g->lt_val, g->ocol16};
+                    g->run_us, g->lt_key, g->lt_val, g->ocol16, g->rowinfo};
     for (void *p : arrs) tc_dev_free(p, s);
 }
 
@@ -532,14 +532,15 @@ tc_status tc_graph_device_bytes(const tc_graph *g, int64_t *bytes) {
 int64_t tc_estimate_device_bytes(int64_t P, int32_t n) {
     if (P < 0 || n < 0) return -1;
     // resident: edges 8m, sym CSR 8(n+1) + 16m (filled on demand), ranks
-    // 8n, oriented 8(n+1) + 8m (+ 2m for its 16-bit copy), supports 8m,
+    // 8n, oriented 8(n+1) + 8m (+ 2m for its 16-bit copy, 16n for the
+    // per-row records of the middle pivot), supports 8m,
     // flags 2m, results 24n; peak temporaries of the build: pair keys 16P +
     // flags 4P (+ staged host pairs 8P).  The middle pivot's transposition
     // (8m) and bit matrices (one bit per oriented wedge) reuse the build's
     // temporaries; denser graphs need more for the bits (see the header).
     const int64_t m = P;
     return 8 * m + 8 * (int64_t)n + 16 * m + 8 * (int64_t)n + 8 * (int64_t)n + 8 * m + 2 * m +
-           8 * m + 2 * m + 24 * (int64_t)n + 28 * P + (64ll << 20);
+           8 * m + 2 * m + 24 * (int64_t)n + 16 * (int64_t)n + 28 * P + (64ll << 20);
 }
 
 void tc_graph_destroy(tc_graph *g) {

@@ -281,11 +281,10 @@ __device__ void bitmap_build(uint2 *bm, uint32_t *scan, const int32_t *__restric
 // GL lanes take the group (a whole wavefront for GL = 64, or one of its
 // 64 / GL groups, each with its own arrays and counters); at most GL pairs.
 template <int LK, int GL = TC_WAVE, bool N16 = false>
-__device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
-                                          const int32_t *__restrict__ ocol,
+__device__ __forceinline__ void mid_group(const int32_t *__restrict__ ocol,
                                           const uint16_t *__restrict__ ocol16,
                                           const uint64_t *__restrict__ in_pair,
-                                          const int64_t *__restrict__ rowbase, int64_t g0,
+                                          const uint4 *__restrict__ rowinfo, int64_t g0,
                                           int64_t gend, const RowTable &t, const BitmapRow &bmr,
                                           uint32_t hmax,
                                           uint32_t *lsup, int64_t vstart, int dv, int64_t *gx,
@@ -301,13 +300,16 @@ __device__ __forceinline__ void mid_group(const int64_t *__restrict__ orp,
         const uint64_t pr = in_pair[i];
         const int64_t k = (int64_t)(uint32_t)pr;
         const int32_t u = (int32_t)(pr >> 32);
-        const int64_t rs = orp[u];
-        const int64_t d = orp[u + 1] - rs;
+        // the row's start and end in ocol and its bit matrix's first
+        // word, in one 16-byte record
+        const uint4 ri = rowinfo[u];
+        const int64_t rs = ri.z;
+        const int64_t d = (int64_t)ri.w - rs;
         const int64_t ii = k - rs;
         const int64_t tail = d - 1 - ii;
         words = (tail + 31) >> 5;
         gs[lane] = k + 1;
-        gb[lane] = rowbase[u] + bit_words(d) - bit_words(d - ii);
+        gb[lane] = (int64_t)(((uint64_t)ri.y << 32) | ri.x) + bit_words(d) - bit_words(d - ii);
         gt[lane] = (int32_t)tail;
     }
     int64_t incl = words;
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ o
                                                    const int32_t *__restrict__ ocol,
                                                    const int64_t *__restrict__ in_ptr,
                                                    const uint64_t *__restrict__ in_pair,
-                                                   const int64_t *__restrict__ rowbase,
+                                                   const uint4 *__restrict__ rowinfo,
                                                    uint32_t *__restrict__ bits,
                                                    const int32_t *__restrict__ item_v,
                                                    const uint32_t *__restrict__ item_first,
@@ -481,12 +483,12 @@ __global__ __launch_bounds__(1024) void k_mid_wave(const int64_t *__restrict__ o
         const uint32_t hmax = (uint32_t)ocol[vstart + d - 1] - rel;
         for (int64_t g0 = first; g0 < pend; g0 += TC_WAVE) {
             if (n16)
-                mid_group<LK_HASH, TC_WAVE, true>(orp, ocol, ocol16, in_pair, rowbase, g0,
+                mid_group<LK_HASH, TC_WAVE, true>(ocol, ocol16, in_pair, rowinfo, g0,
                                                   min(g0 + TC_WAVE, pend), t,
                                                   BitmapRow{nullptr, 0, 0}, hmax, lsup, vstart, d,
                                                   gx, gs, gb, gt, bits, osup, found);
             else
-                mid_group<LK_HASH>(orp, ocol, nullptr, in_pair, rowbase, g0,
+                mid_group<LK_HASH>(ocol, nullptr, in_pair, rowinfo, g0,
                                    min(g0 + TC_WAVE, pend), t, BitmapRow{nullptr, 0, 0}, hmax,
                                    lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
         }
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(256, 4) void k_mid_groups(const int64_t *__restrict
                                                     const int32_t *__restrict__ ocol,
                                                     const int64_t *__restrict__ in_ptr,
                                                     const uint64_t *__restrict__ in_pair,
-                                                    const int64_t *__restrict__ rowbase,
+                                                    const uint4 *__restrict__ rowinfo,
                                                     uint32_t *__restrict__ bits,
                                                     const int32_t *__restrict__ item_v,
                                                     const uint32_t *__restrict__ item_first,
@@ -555,7 +557,7 @@ __global__ __launch_bounds__(256, 4) void k_mid_groups(const int64_t *__restrict
         for (int j = lane; j < d; j += GL) table_insert(t, (uint32_t)ocol[vstart + j], j);
         const uint32_t hmax = (uint32_t)ocol[vstart + d - 1];
         for (int64_t g0 = first; g0 < pend; g0 += GL)
-            mid_group<LK_HASH, GL>(orp, ocol, nullptr, in_pair, rowbase, g0, min(g0 + GL, pend), t,
+            mid_group<LK_HASH, GL>(ocol, nullptr, in_pair, rowinfo, g0, min(g0 + GL, pend), t,
                                    BitmapRow{nullptr, 0, 0}, hmax, lsup, vstart, d, gx, gs, gb, gt,
                                    bits, osup, found);
         for (int j = lane; j < d; j += GL) {
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ ocol,
                                                     const int64_t *__restrict__ in_ptr,
                                                     const uint64_t *__restrict__ in_pair,
-                                                    const int64_t *__restrict__ rowbase,
+                                                    const uint4 *__restrict__ rowinfo,
                                                     uint32_t *__restrict__ bits,
                                                     const int32_t *__restrict__ item_v,
                                                     const uint32_t *__restrict__ item_first,
@@ -652,7 +654,7 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
         for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE) {
             if constexpr (LK == LK_BITMAP) {
                 if (n16 && wide16 && bitmap_words >= BITMAP16_WORDS) {
-                    mid_group<LK_BITMAP16, TC_WAVE, true>(orp, ocol, ocol16, in_pair, rowbase, g0,
+                    mid_group<LK_BITMAP16, TC_WAVE, true>(ocol, ocol16, in_pair, rowinfo, g0,
                                                           min(g0 + TC_WAVE, pend), t, bmr, hmax,
                                                           lsup, vstart, d, gx, gs, gb, gt, bits,
                                                           osup, found);
@@ -661,13 +663,13 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
             }
             if constexpr (LK != LK_GLOBAL) {
                 if (n16) {
-                    mid_group<LK, TC_WAVE, true>(orp, ocol, ocol16, in_pair, rowbase, g0,
+                    mid_group<LK, TC_WAVE, true>(ocol, ocol16, in_pair, rowinfo, g0,
                                                  min(g0 + TC_WAVE, pend), t, bmr, hmax, lsup,
                                                  vstart, d, gx, gs, gb, gt, bits, osup, found);
                     continue;
                 }
             }
-            mid_group<LK>(orp, ocol, nullptr, in_pair, rowbase, g0, min(g0 + TC_WAVE, pend), t,
+            mid_group<LK>(ocol, nullptr, in_pair, rowinfo, g0, min(g0 + TC_WAVE, pend), t,
                           bmr, hmax, lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
         }
         if constexpr (LK != LK_GLOBAL) {
@@ -1130,6 +1132,16 @@ tc_status tc_mid_prepare(tc_graph *g, hipStream_t s) {
     return bit_rows_prepare(g, s);
 }
 
+// Per row: its bit matrix's first word (low, high), its start and end in
+// ocol (below 2^32: the slots number m).
+__global__ void k_row_info(int32_t n, const int64_t *__restrict__ orp,
+                           const int64_t *__restrict__ rowbase, uint4 *__restrict__ ri) {
+    GRID_STRIDE(r, n) {
+        const uint64_t b = (uint64_t)rowbase[r];
+        ri[r] = make_uint4((uint32_t)b, (uint32_t)(b >> 32), (uint32_t)orp[r], (uint32_t)orp[r + 1]);
+    }
+}
+
 // Bit matrices: rowbase = exclusive scan of each row's word count.
 static tc_status bit_rows_prepare(tc_graph *g, hipStream_t s) {
     if (g->rowbase) return TC_OK;
@@ -1147,6 +1159,11 @@ static tc_status bit_rows_prepare(tc_graph *g, hipStream_t s) {
     TC_HIP(hipStreamSynchronize(s));
     g->bit_words = words;
     TC_TRY(tc_graph_alloc(g, &g->hitbits, words, s));
+    TC_TRY(tc_graph_alloc(g, &g->rowinfo, nn, s));
+    if (n > 0) {
+        k_row_info<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->rowbase, g->rowinfo);
+        TC_LAUNCHED();
+    }
     return TC_OK;
 }
 
@@ -1245,7 +1262,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = tc_div_up(n_group, gpb);
         if (blocks > 262144) blocks = 262144;
         k_mid_groups<GROUP_LANES><<<(unsigned)blocks, 256, (size_t)gpb * mid_group_bytes(gmax, GROUP_LANES), s>>>(
-            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, pl[P_GROUP].item_v,
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, pl[P_GROUP].item_v,
             pl[P_GROUP].item_first, n_group, gmax, group_pairs, g->osup, found);
         TC_LAUNCHED();
     }
@@ -1256,7 +1273,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = tc_div_up(n_wave, wpb);
         if (blocks > 262144) blocks = 262144;
         k_mid_wave<<<(unsigned)blocks, wpb * TC_WAVE, (size_t)wpb * per_wave, s>>>(
-            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, wv_v, wv_f, n_wave,
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, wv_v, wv_f, n_wave,
             light_max, wave_pairs, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
@@ -1264,7 +1281,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         const size_t lds = mid_block_bytes(light_max, wpb_block, LK_BITMAP, bw);
         int64_t blocks = n_lbitmap < 1048576 ? n_lbitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
-            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, lb_v, lb_f, n_lbitmap,
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, lb_v, lb_f, n_lbitmap,
             light_max, block_pairs, bw, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
@@ -1274,7 +1291,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         const size_t lds = mid_block_bytes(hmax, wpb_block, LK_BITMAP, bw);
         int64_t blocks = n_bitmap < 1048576 ? n_bitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
-            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bm_v, bm_f, n_bitmap,
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, bm_v, bm_f, n_bitmap,
             hmax, block_pairs, bw, 1, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
@@ -1283,7 +1300,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         const size_t lds = mid_block_bytes(hmax, wpb_block, LK_HASH, 0);
         int64_t blocks = n_block < 1048576 ? n_block : 1048576;
         k_mid_block<LK_HASH><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
-            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, bl_v, bl_f, n_block, hmax,
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, bl_v, bl_f, n_block, hmax,
             block_pairs, 0, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
@@ -1292,7 +1309,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         const size_t lds = mid_block_bytes(0, wpb_block, LK_GLOBAL, 0);
         int64_t blocks = n_huge < 1048576 ? n_huge : 1048576;
         k_mid_block<LK_GLOBAL><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
-            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowbase, g->hitbits, hu_v, hu_f, n_huge, 0,
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, hu_v, hu_f, n_huge, 0,
             block_pairs, 0, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }

@@ -159,6 +159,7 @@ struct tc_graph {
     // per-row triangular bit matrices of the middle-pivot scan
     int64_t *rowbase = nullptr;                     // [n+1] first word of each row's matrix
     uint32_t *hitbits = nullptr;                    // [bit_words]
+    uint4 *rowinfo = nullptr;                       // [n] rowbase (low, high), row start, row end
     int64_t bit_words = 0;
     // results
     uint32_t *osup = nullptr;                       // [m] support per oriented slot
