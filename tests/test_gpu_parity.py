@@ -293,12 +293,15 @@ def test_top_k_ranking(tclib):
     g.close()
 
 
-def test_batch_equals_single(tclib):
-    ns, ms = gg.batched_ba_sizes(40, seed=77, n_hi=3000)
+@pytest.mark.parametrize("algo", [0, 1, 2])
+def test_batch_equals_single(tclib, algo):
+    # about 80 graphs and 86 k vertices in all: under the middle pivot the
+    # batch's top 2^16 ranks (the 16-bit candidates) span many graphs
+    ns, ms = gg.batched_ba_sizes(80, seed=77, n_hi=5000)
     src, dst, po, vo = gg.batched_ba(ns=ns, ms=ms, seed=77)
-    _say("batch of", len(ns))
+    _say("batch of", len(ns), "vertices", int(vo[-1]), "algorithm", algo)
     g = tclib.Graph.batch(src, dst, po, vo)
-    g.compute()
+    g.compute({"algorithm": algo})
     res = g.results()
     eu, ev = g.edges()
     eoff = g.edge_offsets()
