@@ -997,8 +997,33 @@ tc_status rows_write(const tc_graph *g, RowPlan &p, tc_scratch &keep, hipStream_
     return TC_OK;
 }
 
-__global__ void k_zero_words(uint32_t *__restrict__ p, int64_t words) {
-    GRID_STRIDE(i, words) p[i] = 0u;
+// The bit rows of the pairs whose pivot has no higher neighbours: no count
+// kernel scans them (nothing can close), so they are cleared here.  Every
+// other pair's row is written whole by the kernel that scans it, so no
+// other word needs clearing.  One wavefront per item, a lane per pair.
+__global__ void k_zero_rows(const uint4 *__restrict__ rowinfo, const uint64_t *__restrict__ in_pair,
+                            const int64_t *__restrict__ in_ptr, const int32_t *__restrict__ item_v,
+                            const uint32_t *__restrict__ item_first, int64_t nitems, int S,
+                            uint32_t *__restrict__ bits) {
+    const int wpb = blockDim.x / TC_WAVE;
+    const int wv = threadIdx.x / TC_WAVE;
+    const int lane = __lane_id();
+    for (int64_t it = (int64_t)blockIdx.x * wpb + wv; it < nitems; it += (int64_t)gridDim.x * wpb) {
+        const int32_t v = item_v[it];
+        const int64_t first = item_first[it];
+        const int64_t pend = min(first + (int64_t)S, in_ptr[v + 1]);
+        for (int64_t i = first + lane; i < pend; i += TC_WAVE) {
+            const uint64_t pr = in_pair[i];
+            const int64_t k = (int64_t)(uint32_t)pr;
+            const uint4 ri = rowinfo[(int32_t)(pr >> 32)];
+            const int64_t d = (int64_t)ri.w - ri.z;
+            const int64_t ii = k - ri.z;
+            const int64_t words = (d - 1 - ii + 31) >> 5;
+            const int64_t gb = (int64_t)(((uint64_t)ri.y << 32) | ri.x) + bit_words(d) -
+                               bit_words(d - ii);
+            for (int64_t w = 0; w < words; ++w) bits[gb + w] = 0u;
+        }
+    }
 }
 
 __global__ void k_row_words(int32_t n, const int64_t *__restrict__ orp, int64_t *__restrict__ out) {
@@ -1207,7 +1232,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     // 64 / GROUP_LANES to a wavefront, in items of at most GROUP_PAIRS pairs
     const int gmax = light_max < GROUP_DMAX ? light_max : GROUP_DMAX;
     const int group_pairs = wave_pairs < GROUP_PAIRS ? wave_pairs : GROUP_PAIRS;
-    enum { P_GROUP, P_WAVE, P_LBITMAP, P_BITMAP, P_BLOCK, P_HUGE, NPLANS };
+    enum { P_GROUP, P_WAVE, P_LBITMAP, P_BITMAP, P_BLOCK, P_HUGE, P_ZERO, NPLANS };
     ItemPlan pl[NPLANS];
     pl[P_GROUP] = {1, gmax, group_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs};
     pl[P_WAVE] = {gmax + 1, light_max, wave_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs};
@@ -1215,6 +1240,8 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     pl[P_BITMAP] = {light_max + 1, split ? huge_min - 1 : light_max, block_pairs, 1, span_max, 0};
     pl[P_BLOCK] = {light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, 0};
     pl[P_HUGE] = {huge_min, 0x7FFFFFFF, block_pairs, 0, 0, 0};
+    // pivots with an empty row: their pairs' bit rows are only cleared
+    pl[P_ZERO] = {0, 0, wave_pairs, 0, 0, 0};
     RowPlan rp[2];
     rp[0].lo = 2;
     rp[0].hi = 64;
@@ -1249,10 +1276,13 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     g->n_light = n_group + n_wave + n_lbitmap;
     g->n_heavy = n_block + n_bitmap;
     g->n_huge = n_huge;
-    // pairs whose pivot closes nothing are never scanned: their rows stay 0
-    if (g->bit_words > 0) {
-        int64_t zb = tc_div_up(g->bit_words, BK);
-        k_zero_words<<<(unsigned)(zb < 1048576 ? zb : 1048576), BK, 0, s>>>(g->hitbits, g->bit_words);
+    // pairs whose pivot closes nothing are never scanned: their rows are
+    // cleared, and every other word is written by the count
+    if (pl[P_ZERO].count > 0) {
+        int64_t zb = tc_div_up(pl[P_ZERO].count, BK / TC_WAVE);
+        k_zero_rows<<<(unsigned)(zb < 262144 ? zb : 262144), BK, 0, s>>>(
+            g->rowinfo, g->in_pair, g->in_ptr, pl[P_ZERO].item_v, pl[P_ZERO].item_first,
+            pl[P_ZERO].count, wave_pairs, g->hitbits);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 5, s);
