@@ -407,9 +407,7 @@ __global__ void k_dplus_by_rank(int32_t n, const uint32_t *__restrict__ cursor,
 // dispatch.
 template <int GL>
 __device__ __forceinline__ void orient_class(int64_t x0, uint32_t dl, uint32_t lo, uint32_t *wsk,
-                                             const int64_t *__restrict__ row_ptr,
-                                             const int32_t *__restrict__ rank,
-                                             const int64_t *__restrict__ orp,
+                                             int64_t bl, int32_t rl, int64_t ol,
                                              const uint64_t *__restrict__ tbuf,
                                              int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e,
                                              int32_t *__restrict__ orow) {
@@ -427,11 +425,15 @@ __device__ __forceinline__ void orient_class(int64_t x0, uint32_t dl, uint32_t l
         const int j = has ? __ffsll((long long)mm) - 1 : 0;
         for (int q = 0; q < GPW && mask; ++q) mask &= mask - 1;
         const int d = (int)__shfl(dl, j, TC_WAVE);
-        const int64_t x = x0 + j;
+        // the row's bucket start, rank and oriented start, loaded once per
+        // chunk by the lane of the vertex
+        const int64_t bx = __shfl(bl, j, TC_WAVE);
+        const int32_t rx = __shfl(rl, j, TC_WAVE);
+        const int64_t ob = __shfl(ol, j, TC_WAVE);
         const bool mine = has && sl < d;
         uint32_t key = 0xFFFFFFFFu, val = 0;
         if (mine) {
-            const uint64_t w = tbuf[row_ptr[x] + sl];
+            const uint64_t w = tbuf[bx + sl];
             key = (uint32_t)(w >> 32);
             val = (uint32_t)w;
         }
@@ -440,8 +442,7 @@ __device__ __forceinline__ void orient_class(int64_t x0, uint32_t dl, uint32_t l
         if (mine) {
             int pos = 0;
             for (int t = 0; t < d; ++t) pos += gsk[t] < key ? 1 : 0;
-            const int32_t rx = rank[x];
-            const int64_t k = orp[rx] + pos;
+            const int64_t k = ob + pos;
             ocol[k] = (int32_t)key;
             o2e[k] = val;
             orow[k] = rx;
@@ -455,10 +456,8 @@ __device__ __forceinline__ void orient_class(int64_t x0, uint32_t dl, uint32_t l
 // LDS one at a time, the same word for every lane).
 template <int E>
 __device__ __forceinline__ void orient_class_wide(int64_t x0, uint32_t dl, uint32_t lo,
-                                                  uint32_t *wsk, const int64_t *__restrict__ row_ptr,
-                                                  const int32_t *__restrict__ rank,
-                                                  const int64_t *__restrict__ orp,
-                                                  const uint64_t *__restrict__ tbuf,
+                                                  uint32_t *wsk, int64_t bl, int32_t rl,
+                                                  int64_t ol, const uint64_t *__restrict__ tbuf,
                                                   int32_t *__restrict__ ocol,
                                                   uint32_t *__restrict__ o2e,
                                                   int32_t *__restrict__ orow) {
@@ -468,8 +467,9 @@ __device__ __forceinline__ void orient_class_wide(int64_t x0, uint32_t dl, uint3
         const int j = __ffsll((long long)mask) - 1;
         mask &= mask - 1;
         const int d = (int)__shfl(dl, j, TC_WAVE);
-        const int64_t x = x0 + j;
-        const int64_t b = row_ptr[x];
+        const int64_t b = __shfl(bl, j, TC_WAVE);
+        const int32_t rx = __shfl(rl, j, TC_WAVE);
+        const int64_t ob = __shfl(ol, j, TC_WAVE);
         uint32_t key[E], val[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -492,8 +492,6 @@ __device__ __forceinline__ void orient_class_wide(int64_t x0, uint32_t dl, uint3
 #pragma unroll
             for (int e = 0; e < E; ++e) pos[e] += kt < key[e] ? 1 : 0;
         }
-        const int32_t rx = rank[x];
-        const int64_t ob = orp[rx];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             if (lane + TC_WAVE * e < d) {
@@ -518,12 +516,21 @@ __global__ __launch_bounds__(256) void k_orient_small(
     for (int64_t x0 = ((int64_t)blockIdx.x * 4 + wv) * TC_WAVE; x0 < n; x0 += nwaves * TC_WAVE) {
         const int64_t xl = x0 + lane;
         const uint32_t dl = xl < n ? cursor[xl] : 0u;
-        orient_class<8>(x0, dl, 0, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
-        orient_class<16>(x0, dl, 8, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
-        orient_class<32>(x0, dl, 16, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
-        orient_class<64>(x0, dl, 32, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
-        orient_class_wide<2>(x0, dl, 64, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
-        orient_class_wide<4>(x0, dl, 128, sk[wv], row_ptr, rank, orp, tbuf, ocol, o2e, orow);
+        // each lane's vertex: bucket start, rank, oriented row start (the
+        // rows of every class in this chunk read them from here)
+        int64_t bl = 0, ol = 0;
+        int32_t rl = 0;
+        if (dl > 0) {
+            bl = row_ptr[xl];
+            rl = rank[xl];
+            ol = orp[rl];
+        }
+        orient_class<8>(x0, dl, 0, sk[wv], bl, rl, ol, tbuf, ocol, o2e, orow);
+        orient_class<16>(x0, dl, 8, sk[wv], bl, rl, ol, tbuf, ocol, o2e, orow);
+        orient_class<32>(x0, dl, 16, sk[wv], bl, rl, ol, tbuf, ocol, o2e, orow);
+        orient_class<64>(x0, dl, 32, sk[wv], bl, rl, ol, tbuf, ocol, o2e, orow);
+        orient_class_wide<2>(x0, dl, 64, sk[wv], bl, rl, ol, tbuf, ocol, o2e, orow);
+        orient_class_wide<4>(x0, dl, 128, sk[wv], bl, rl, ol, tbuf, ocol, o2e, orow);
     }
 }
 
