@@ -580,19 +580,99 @@ __global__ __launch_bounds__(256) void k_orient_block(
     }
 }
 
-// One wavefront per listed vertex with SEG_SMALL < entries <= SEG_MID: the
-// same bitonic sort over an LDS buffer of the wavefront's own, so its rounds
-// need no workgroup barrier (a wavefront's LDS operations stay in order).
+// One wavefront per listed vertex with SEG_SMALL < entries <= SEG_MID: a
+// bitonic sort over an LDS buffer of the wavefront's own, so its rounds need
+// no workgroup barrier (a wavefront's LDS operations stay in order).
 constexpr int SEG_MID = 1024;
+
+// Bitonic compare-exchange of stage (k, J) on a lane's E consecutive
+// elements (global index base + i), for partners inside the lane (J < E).
+template <int E, int J>
+__device__ __forceinline__ void bitonic_in_lane(uint64_t (&r)[E], int base, int k) {
+    if constexpr (J < E) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            if ((i & J) == 0) {
+                const bool up = ((base + i) & k) == 0;
+                const uint64_t va = r[i], vb = r[i + J];
+                const bool sw = (va > vb) == up;
+                r[i] = sw ? vb : va;
+                r[i + J] = sw ? va : vb;
+            }
+        }
+    }
+}
+
+// One bucket of E * 64 slots (its d entries, padded with all-ones words),
+// sorted by one wavefront: each lane keeps E consecutive elements in
+// registers, the stages whose partners lie E or more apart go through LDS
+// (one store and one load per merge size k), the others stay in registers.
+// Slot i sits at LDS word i + i / E, so the lanes' runs of E start in
+// different banks.
+template <int E>
+__device__ __forceinline__ void orient_mid_row(uint64_t *sk, int d, int64_t b, int32_t rx,
+                                               int64_t ob, const uint64_t *__restrict__ tbuf,
+                                               int32_t *__restrict__ ocol,
+                                               uint32_t *__restrict__ o2e,
+                                               int32_t *__restrict__ orow) {
+    constexpr int P = E * TC_WAVE;
+    const int lane = __lane_id();
+    const int base = E * lane;
+    auto px = [](int i) { return i + i / E; };
+    for (int j = lane; j < P; j += TC_WAVE) sk[px(j)] = j < d ? tbuf[b + j] : ~0ull;
+    __builtin_amdgcn_wave_barrier();
+    uint64_t r[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) r[i] = sk[px(base) + i];
+    for (int k = 2; k <= P; k <<= 1) {
+        if (k > E) {
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int i = 0; i < E; ++i) sk[px(base) + i] = r[i];
+            __builtin_amdgcn_wave_barrier();
+            for (int j = k >> 1; j >= E; j >>= 1) {
+                for (int t = lane; t < (P >> 1); t += TC_WAVE) {
+                    const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                    const uint64_t va = sk[px(a)], vb = sk[px(a + j)];
+                    const bool up = (a & k) == 0;
+                    if ((va > vb) == up) {
+                        sk[px(a)] = vb;
+                        sk[px(a + j)] = va;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+#pragma unroll
+            for (int i = 0; i < E; ++i) r[i] = sk[px(base) + i];
+        }
+        // partners inside the lane: J from min(k / 2, E / 2) down to 1
+        const int jtop = (k >> 1) < E ? (k >> 1) : (E >> 1);
+        if (jtop >= 8) bitonic_in_lane<E, 8>(r, base, k);
+        if (jtop >= 4) bitonic_in_lane<E, 4>(r, base, k);
+        if (jtop >= 2) bitonic_in_lane<E, 2>(r, base, k);
+        bitonic_in_lane<E, 1>(r, base, k);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < E; ++i) sk[px(base) + i] = r[i];
+    __builtin_amdgcn_wave_barrier();
+    for (int t = lane; t < d; t += TC_WAVE) {
+        const uint64_t w = sk[px(t)];
+        ocol[ob + t] = (int32_t)(w >> 32);
+        o2e[ob + t] = (uint32_t)w;
+        orow[ob + t] = rx;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
 
 __global__ __launch_bounds__(256) void k_orient_mid(
     const int32_t *__restrict__ list, int64_t nlist, const int64_t *__restrict__ row_ptr,
     const uint32_t *__restrict__ cursor, const int32_t *__restrict__ rank,
     const int64_t *__restrict__ orp, const uint64_t *__restrict__ tbuf,
     int32_t *__restrict__ ocol, uint32_t *__restrict__ o2e, int32_t *__restrict__ orow) {
-    __shared__ uint64_t sk_all[4][SEG_MID];
+    static_assert(SEG_SMALL == 256 && SEG_MID == 1024, "rows of 257..1024 entries: 512 or 1024 slots");
+    __shared__ uint64_t sk_all[4][SEG_MID + SEG_MID / 8];
     const int wv = threadIdx.x / TC_WAVE;
-    const int lane = __lane_id();
     uint64_t *sk = sk_all[wv];
     const int64_t waves = (int64_t)gridDim.x * 4;
     for (int64_t i = (int64_t)blockIdx.x * 4 + wv; i < nlist; i += waves) {
@@ -601,31 +681,10 @@ __global__ __launch_bounds__(256) void k_orient_mid(
         const int64_t ob = orp[rx];
         const int d = (int)cursor[x];
         const int64_t b = row_ptr[x];
-        int P = 1;
-        while (P < d) P <<= 1;
-        for (int j = lane; j < P; j += TC_WAVE) sk[j] = j < d ? tbuf[b + j] : ~0ull;
-        __builtin_amdgcn_wave_barrier();
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = lane; t < (P >> 1); t += TC_WAVE) {
-                    const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                    const uint64_t va = sk[a], vb = sk[a + j];
-                    const bool up = (a & k) == 0;
-                    if ((va > vb) == up) {
-                        sk[a] = vb;
-                        sk[a + j] = va;
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-        for (int t = lane; t < d; t += TC_WAVE) {
-            const uint64_t w = sk[t];
-            ocol[ob + t] = (int32_t)(w >> 32);
-            o2e[ob + t] = (uint32_t)w;
-            orow[ob + t] = rx;
-        }
-        __builtin_amdgcn_wave_barrier();
+        if (d <= SEG_MID / 2)
+            orient_mid_row<SEG_MID / 2 / TC_WAVE>(sk, d, b, rx, ob, tbuf, ocol, o2e, orow);
+        else
+            orient_mid_row<SEG_MID / TC_WAVE>(sk, d, b, rx, ob, tbuf, ocol, o2e, orow);
     }
 }
 
