@@ -64,12 +64,17 @@ __host__ __device__ __forceinline__ int64_t bit_words(int64_t d) {
 
 // bit_words in the index type I of the fold: 32-bit for rows below
 // FOLD_I32_MAX entries (every offset inside such a B_u fits), 64-bit
-// otherwise.
+// otherwise.  With 32-bit indices x < 2^15, so q < 2^10 and both products
+// are exact in the full-rate 24-bit multiply.
 template <typename I>
 __device__ __forceinline__ I bit_words_t(I x) {
     if (x < 2) return 0;
     const I q = (x - 1) >> 5, r = (x - 1) & 31;
-    return 32 * (q * (q + 1) / 2) + (q + 1) * r;
+    if constexpr (sizeof(I) == 4)
+        return (I)(32u * (__umul24((uint32_t)q, (uint32_t)q + 1u) >> 1) +
+                   __umul24((uint32_t)q + 1u, (uint32_t)r));
+    else
+        return 32 * (q * (q + 1) / 2) + (q + 1) * r;
 }
 constexpr int64_t FOLD_I32_MAX = 32768;
 
@@ -799,8 +804,7 @@ __device__ __forceinline__ void csa(uint32_t a, uint32_t b, uint32_t c, uint32_t
 // row words the stripe can touch, already loaded.
 __device__ __forceinline__ uint32_t stripe_bits(int o, uint32_t lo, uint32_t hi) {
     if (o < 0) return lo << (int)(-o);
-    const int sh = (int)(o & 31);
-    return sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
+    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)o & 31u);  // (hi:lo) >> (o mod 32)
 }
 
 // Big rows (|N_H(u)| > 64): one wavefront per row u.
