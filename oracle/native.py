@@ -26,6 +26,16 @@ class OracleError(RuntimeError):
     pass
 
 
+def host_threads(cap=16):
+    """Threads for a full oracle run: the CPUs this process may use, at most
+    ``cap`` (a GPU machine grants one GPU's process 16 host threads)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count() or 1
+    return max(1, min(cap, avail))
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -97,7 +107,7 @@ def _run(which, src, dst, n, nthreads, row_stride=1, phases=None):
 
 def o1_definition(src, dst, n, nthreads=None):
     """O1: per-edge common neighbours, then Definition 1 (integer form)."""
-    return _run(1, src, dst, int(n), nthreads or os.cpu_count() or 1)
+    return _run(1, src, dst, int(n), nthreads or host_threads())
 
 
 def o2_paper(src, dst, n, nthreads=None, row_stride=1, phases=None):
@@ -108,7 +118,7 @@ def o2_paper(src, dst, n, nthreads=None, row_stride=1, phases=None):
     ``phases`` (a list) receives the seconds spent in normalisation,
     ordering, counting and aggregation.
     """
-    return _run(2, src, dst, int(n), nthreads or os.cpu_count() or 1, row_stride, phases)
+    return _run(2, src, dst, int(n), nthreads or host_threads(), row_stride, phases)
 
 
 class PointQuery:

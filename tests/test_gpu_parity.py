@@ -191,12 +191,22 @@ def test_sixteen_bit_candidates_both_sides_in_one_launch(tclib):
         assert_parity(run_gpu(tclib, src, dst, n, tuning=tuning), ref)
 
 
-def test_rmat_s20_full_parity(tclib):
+@pytest.fixture(scope="module")
+def rmat_s20():
     src, dst, n = gg.rmat(20, 16, seed=20)
     _say("R-MAT s20 oracle")
-    ref = native.o1_definition(src, dst, n)
-    _say("R-MAT s20 gpu")
-    assert_parity(run_gpu(tclib, src, dst, n), ref)
+    return src, dst, n, native.o1_definition(src, dst, n)
+
+
+@pytest.mark.parametrize("tuning_name", [None, "rmat_s24_ef16", "batched_ba4096"])
+def test_rmat_s20_full_parity(tclib, rmat_s20, tuning_name):
+    # library defaults, and the stored schedules the benchmark times on the
+    # scale-24 graph and on the batch, all against the full definition
+    from paper_2105_00110_amd import autotune
+    src, dst, n, ref = rmat_s20
+    tuning = autotune.load(tuning_name) if tuning_name else None
+    _say("R-MAT s20 gpu, tuning", tuning_name, tuning)
+    assert_parity(run_gpu(tclib, src, dst, n, tuning=tuning), ref)
 
 
 def test_determinism_two_runs(tclib):
