@@ -180,6 +180,73 @@ tc_status tc_batch_create(const int32_t *src, const int32_t *dst, const int64_t 
                           const int64_t *graph_vtx_off, int32_t num_graphs, int32_t mem_kind,
                           void *stream, tc_graph **out);
 
+/* ------------------------------------------------------------------------
+ * Fused batch of small graphs: one persistent launch runs the whole path
+ * (deduplication, degree order, orientation, counting with support, △(v),
+ * △(G), Algorithm 2's numerator and the quotient of Definition 1) for every
+ * graph of a batch, one workgroup per graph at a time, pulling graphs from
+ * a device-side queue.  The counting step is the appendix's Procedure 2
+ * (sorted N_H lists merged, counts in place of marks), one thread per
+ * oriented edge.  Results equal tc_batch_create + tc_compute exactly.
+ *
+ * For callers that cannot allocate or read back: it allocates nothing (the
+ * caller passes a workspace), never synchronises the stream and reads
+ * nothing back, so the call can be captured into a HIP graph and replayed
+ * (each replay recomputes from the inputs in place).
+ *
+ * All pointers are device memory of the current device, except tuning.
+ *   src, dst             pairs, ids LOCAL to their graph (0..n_g-1)
+ *   graph_pair_off[G+1]  graph g owns pairs [graph_pair_off[g], graph_pair_off[g+1])
+ *   graph_vtx_off[G+1]   graph g owns vertices [graph_vtx_off[g], graph_vtx_off[g+1])
+ *                        of the outputs below; both arrays start at 0 and end at
+ *                        num_pairs and num_vertices
+ *   order[G]             optional (NULL = 0..G-1): the order in which graphs are
+ *                        taken from the queue, e.g. largest first
+ *   num_pairs, num_vertices  the totals (host values, used to size and bound)
+ * Outputs (eu, ev, support, tri, triG, num, tc may each be NULL):
+ *   eu[P], ev[P], support[P]  graph g's canonical edges (u < v, local ids, in
+ *                        lexicographic order) and their support at positions
+ *                        graph_pair_off[g] .. graph_pair_off[g] + num_edges[g] - 1;
+ *                        the rest of the range is not written
+ *   num_edges[G]         m_g after deduplication (required)
+ *   tri[N], num[N], tc[N]  per vertex, at graph_vtx_off[g] + local id
+ *   triG[G]              △ of each graph
+ *   status[G]            (required) TC_OK; TC_TRIANGLE_FREE when △(G) = 0 (tc = 0);
+ *                        TC_ERR_VERTEX_RANGE if a pair of the graph has an id outside
+ *                        [0, n_g); TC_ERR_UNSUPPORTED if n_g > 65535;
+ *                        TC_ERR_INVALID_ARG for offsets outside the arrays or
+ *                        decreasing.  A graph with an error gets no edges and zero
+ *                        tri / num / tc (nothing at all for invalid offsets).
+ *   workspace            device memory of at least
+ *                        tc_batch_fused_workspace_bytes(num_pairs, num_vertices, G)
+ *                        bytes, 256-byte aligned, used by this call only until
+ *                        the stream passes it (no need to clear it)
+ * Returns TC_ERR_INVALID_ARG for a NULL required pointer, a negative size, a
+ * short or misaligned workspace or a bad tuning, TC_ERR_UNSUPPORTED beyond
+ * 2^40 pairs or vertices, TC_ERR_DEVICE if a launch fails; otherwise TC_OK
+ * once the work is queued on `stream` (per-graph outcomes are in status[]).
+ * Two calls sharing a workspace must not overlap in time.
+ *
+ * tc_fused_tuning: block (256, 512 or 1024 threads per workgroup) and
+ * wg_per_cu (1..16 persistent workgroups per compute unit).
+ * ---------------------------------------------------------------------- */
+typedef struct tc_fused_tuning {
+    int32_t block;
+    int32_t wg_per_cu;
+} tc_fused_tuning;
+
+tc_status tc_fused_tuning_default(tc_fused_tuning *t);
+
+/* Workspace bytes of tc_batch_fused (-1 for negative sizes). */
+int64_t tc_batch_fused_workspace_bytes(int64_t num_pairs, int64_t num_vertices, int32_t num_graphs);
+
+tc_status tc_batch_fused(const int32_t *src, const int32_t *dst, const int64_t *graph_pair_off,
+                         const int64_t *graph_vtx_off, const int32_t *order, int32_t num_graphs,
+                         int64_t num_pairs, int64_t num_vertices, int32_t *eu, int32_t *ev,
+                         uint64_t *support, int64_t *num_edges, uint64_t *tri, uint64_t *triG,
+                         uint64_t *num, double *tc, int32_t *status, void *workspace,
+                         int64_t workspace_bytes, const tc_fused_tuning *tuning, void *stream);
+
 /* Number of graphs in the handle (1 for a single graph). */
 int32_t tc_num_graphs(const tc_graph *g);
 

@@ -30,6 +30,7 @@ HIP_SOURCES = [
     "tc_aggregate.hip",
     "tc_algebraic.hip",
     "tc_ingest.hip",
+    "tc_fused.hip",
     "tc_api.hip",
 ]
 

@@ -56,6 +56,13 @@ class tc_tuning(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class tc_fused_tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -68,6 +75,10 @@ _SIGS = {
     "tc_graph_from_edges": (_st, [_vp, _vp, _i64, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
     "tc_graph_from_csr": (_st, [_vp, _vp, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
     "tc_batch_create": (_st, [_vp, _vp, _vp, _vp, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
+    "tc_fused_tuning_default": (_st, [ctypes.POINTER(tc_fused_tuning)]),
+    "tc_batch_fused_workspace_bytes": (_i64, [_i64, _i64, _i32]),
+    "tc_batch_fused": (_st, [_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp,
+                             _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(tc_fused_tuning), _vp]),
     "tc_num_graphs": (_i32, [_vp]),
     "tc_batch_edge_offsets": (_st, [_vp, _vp]),
     "tc_compute": (_st, [_vp, _vp]),
@@ -155,6 +166,27 @@ def tc_batch_create(src, dst, graph_pair_off, graph_vtx_off, num_graphs, mem_kin
     _check(load().tc_batch_create(src, dst, graph_pair_off, graph_vtx_off, int(num_graphs),
                                   int(mem_kind), stream, ctypes.byref(h)), "tc_batch_create")
     return h
+
+
+def tc_fused_tuning_default():
+    t = tc_fused_tuning()
+    _check(load().tc_fused_tuning_default(ctypes.byref(t)), "tc_fused_tuning_default")
+    return t
+
+
+def tc_batch_fused_workspace_bytes(num_pairs, num_vertices, num_graphs):
+    return int(load().tc_batch_fused_workspace_bytes(int(num_pairs), int(num_vertices),
+                                                      int(num_graphs)))
+
+
+def tc_batch_fused(src, dst, graph_pair_off, graph_vtx_off, order, num_graphs, num_pairs,
+                   num_vertices, eu, ev, support, num_edges, tri, triG, num, tc, status, workspace,
+                   workspace_bytes, tuning, stream):
+    return _check(load().tc_batch_fused(
+        src, dst, graph_pair_off, graph_vtx_off, order, int(num_graphs), int(num_pairs),
+        int(num_vertices), eu, ev, support, num_edges, tri, triG, num, tc, status, workspace,
+        int(workspace_bytes), ctypes.byref(tuning) if tuning is not None else None, stream),
+        "tc_batch_fused")
 
 
 def tc_num_graphs(h):
@@ -472,6 +504,89 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class FusedBatch:
+    """Device buffers for ``tc_batch_fused`` over one batch layout.
+
+    ``src``/``dst`` are device int32 tensors of local ids; ``pair_off`` and
+    ``vtx_off`` host arrays of G+1 offsets.  ``order`` is "largest_first"
+    (graphs taken by pair count, largest first), None (index order) or an
+    explicit permutation.  ``run()`` queues the one launch (plus the queue
+    reset) on ``stream`` and allocates nothing, so it can be captured in a
+    CUDA/HIP graph.  Outputs stay on the device in the attributes named like
+    the C arguments (uint64 data in int64 tensors).
+    """
+
+    def __init__(self, src, dst, pair_off, vtx_off, order="largest_first", tuning=None,
+                 stream=None):
+        import torch
+        dev = src.device
+        po = np.ascontiguousarray(pair_off, np.int64)
+        vo = np.ascontiguousarray(vtx_off, np.int64)
+        self.G = int(po.shape[0] - 1)
+        self.P = int(po[-1])
+        self.N = int(vo[-1])
+        self.h_pair_off, self.h_vtx_off = po, vo
+        self.src = src.to(torch.int32).contiguous()
+        self.dst = dst.to(torch.int32).contiguous()
+        self.pair_off = torch.from_numpy(po).to(dev)
+        self.vtx_off = torch.from_numpy(vo).to(dev)
+        if isinstance(order, str) and order == "largest_first":
+            order = np.argsort(-np.diff(po), kind="stable").astype(np.int32)
+        self.order = None if order is None else torch.from_numpy(
+            np.ascontiguousarray(order, np.int32)).to(dev)
+        if tuning is None or isinstance(tuning, tc_fused_tuning):
+            self.tuning = tuning
+        else:
+            self.tuning = tc_fused_tuning_default()
+            for k, v in tuning.items():
+                setattr(self.tuning, k, int(v))
+        self.stream = stream if stream is not None else current_stream()
+        P1, N1, G1 = max(self.P, 1), max(self.N, 1), max(self.G, 1)
+        self.eu = torch.empty(P1, dtype=torch.int32, device=dev)
+        self.ev = torch.empty(P1, dtype=torch.int32, device=dev)
+        self.support = torch.empty(P1, dtype=torch.int64, device=dev)
+        self.num_edges = torch.empty(G1, dtype=torch.int64, device=dev)
+        self.tri = torch.empty(N1, dtype=torch.int64, device=dev)
+        self.num = torch.empty(N1, dtype=torch.int64, device=dev)
+        self.tc = torch.empty(N1, dtype=torch.float64, device=dev)
+        self.triG = torch.empty(G1, dtype=torch.int64, device=dev)
+        self.status = torch.empty(G1, dtype=torch.int32, device=dev)
+        self.ws_bytes = tc_batch_fused_workspace_bytes(self.P, self.N, self.G)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws_ptr = self.workspace.data_ptr() + off
+
+    def run(self):
+        return tc_batch_fused(
+            _ptr(self.src), _ptr(self.dst), _ptr(self.pair_off), _ptr(self.vtx_off),
+            _ptr(self.order), self.G, self.P, self.N, _ptr(self.eu), _ptr(self.ev),
+            _ptr(self.support), _ptr(self.num_edges), _ptr(self.tri), _ptr(self.triG),
+            _ptr(self.num), _ptr(self.tc), _ptr(self.status), self.ws_ptr, self.ws_bytes,
+            self.tuning, self.stream)
+
+    def results(self):
+        """Host copies: dict(eu, ev, support, num_edges, tri, triG, num, tc, status)
+        with the C layout (edges at the pair offsets)."""
+        P, N, G = self.P, self.N, self.G
+        out = {"eu": self.eu[:P], "ev": self.ev[:P], "support": self.support[:P],
+               "num_edges": self.num_edges[:G], "tri": self.tri[:N], "triG": self.triG[:G],
+               "num": self.num[:N], "tc": self.tc[:N], "status": self.status[:G]}
+        out = {k: v.cpu().numpy() for k, v in out.items()}
+        for k in ("support", "tri", "triG", "num"):
+            out[k] = out[k].view(np.uint64)
+        return out
+
+    def graph(self, res, g):
+        """Graph g's slice of host results: eu, ev, support (m_g entries),
+        tri, num, tc (n_g entries), triG, status."""
+        pa, va, vb = int(self.h_pair_off[g]), int(self.h_vtx_off[g]), int(self.h_vtx_off[g + 1])
+        m = int(res["num_edges"][g])
+        return {"eu": res["eu"][pa:pa + m], "ev": res["ev"][pa:pa + m],
+                "support": res["support"][pa:pa + m], "tri": res["tri"][va:vb],
+                "num": res["num"][va:vb], "tc": res["tc"][va:vb],
+                "triG": res["triG"][g:g + 1], "status": int(res["status"][g])}
 
 
 def tuning_from_dict(d):

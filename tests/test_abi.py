@@ -46,6 +46,30 @@ def test_host_only_calls():
     assert lib.tc_numerator_algebraic(None, None, 0, None) == tc.TC_ERR_INVALID_ARG
 
 
+def test_fused_argument_checks_on_host():
+    # argument errors are found before any device work
+    lib = tc.load()
+    ft = tc.tc_fused_tuning_default()
+    assert ft.block in (256, 512, 1024) and 1 <= ft.wg_per_cu <= 16
+    assert tc.tc_batch_fused_workspace_bytes(-1, 0, 0) == -1
+    ws = tc.tc_batch_fused_workspace_bytes(1000, 100, 3)
+    assert ws >= 20 * 1000 + 40 * 100
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails its checks
+    args = [fake, fake, fake, fake, None, 3, 1000, 100] + [fake] * 9
+    assert lib.tc_batch_fused(*args, fake, ws - 1, None, None) == tc.TC_ERR_INVALID_ARG
+    assert lib.tc_batch_fused(*args, ctypes.c_void_p((1 << 20) + 8), ws, None,
+                              None) == tc.TC_ERR_INVALID_ARG
+    bad = tc.tc_fused_tuning(block=384, wg_per_cu=2)
+    assert lib.tc_batch_fused(*args, fake, ws, ctypes.byref(bad), None) == tc.TC_ERR_INVALID_ARG
+    neg = [fake, fake, fake, fake, None, -1, 1000, 100] + [fake] * 9
+    assert lib.tc_batch_fused(*neg, fake, ws, None, None) == tc.TC_ERR_INVALID_ARG
+    none_status = args[:16] + [None]
+    assert lib.tc_batch_fused(*none_status, fake, ws, None, None) == tc.TC_ERR_INVALID_ARG
+    # no graphs: nothing to do, nothing touched
+    empty = [None, None, None, None, None, 0, 0, 0] + [None] * 9
+    assert lib.tc_batch_fused(*empty, None, 0, None, None) == tc.TC_OK
+
+
 def test_no_oracle_in_product():
     pkg = os.path.join(ROOT, "paper_2105_00110_amd")
     for dirpath, _, files in os.walk(pkg):
