@@ -247,6 +247,37 @@ tc_status tc_batch_fused(const int32_t *src, const int32_t *dst, const int64_t *
                          uint64_t *num, double *tc, int32_t *status, void *workspace,
                          int64_t workspace_bytes, const tc_fused_tuning *tuning, void *stream);
 
+/* ------------------------------------------------------------------------
+ * tc_batch_fused_noalloc: tc_batch_fused for callers that cannot allocate
+ * device memory or pass a workspace (code under graph capture, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments,
+ * outputs and per-graph statuses as tc_batch_fused, without workspace and
+ * workspace_bytes: the workspace is a fixed device array inside the library
+ * of tc_batch_fused_noalloc_max_bytes() bytes (64 MiB) per GPU, held from
+ * the library's first use on that GPU until the process ends.
+ *   - Returns TC_ERR_BUDGET, with nothing queued, when
+ *     tc_batch_fused_workspace_bytes(num_pairs, num_vertices, num_graphs)
+ *     exceeds that maximum (about 20 bytes per pair plus 40 per vertex).
+ *   - Calls no allocating routine: the array's device address is looked up
+ *     on the first call on each device (hipGetSymbolAddress); every call
+ *     then queues the same two kernels as tc_batch_fused on `stream`.
+ *   - Every call on one GPU uses the same array, which keeps the last
+ *     call's contents (nothing in it needs clearing: each call resets its
+ *     queue counter with a kernel and writes every word before reading it).
+ *     Calls whose work overlaps on one GPU (other streams or host threads
+ *     before the earlier call's work has finished) race on the array and
+ *     give undefined results: serialise them, e.g. on one stream.
+ * ---------------------------------------------------------------------- */
+int64_t tc_batch_fused_noalloc_max_bytes(void);
+
+tc_status tc_batch_fused_noalloc(const int32_t *src, const int32_t *dst,
+                                 const int64_t *graph_pair_off, const int64_t *graph_vtx_off,
+                                 const int32_t *order, int32_t num_graphs, int64_t num_pairs,
+                                 int64_t num_vertices, int32_t *eu, int32_t *ev, uint64_t *support,
+                                 int64_t *num_edges, uint64_t *tri, uint64_t *triG, uint64_t *num,
+                                 double *tc, int32_t *status, const tc_fused_tuning *tuning,
+                                 void *stream);
+
 /* Number of graphs in the handle (1 for a single graph). */
 int32_t tc_num_graphs(const tc_graph *g);
 

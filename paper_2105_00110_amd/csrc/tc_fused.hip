@@ -32,7 +32,11 @@
 //
 // Graphs of at most FUSED_MAX_N vertices qualify (keys stay below 2^32).
 // Nothing is read back to the host and no memory is allocated, so the two
-// launches can be captured in a graph and replayed.
+// launches can be captured in a graph and replayed.  tc_batch_fused takes
+// its workspace from the caller; tc_batch_fused_noalloc uses a fixed device
+// array of this file instead.
+#include <mutex>
+
 #include "tc_internal.h"
 
 namespace {
@@ -513,6 +517,32 @@ tc_status launch(const FusedArgs &a, int wg_per_cu, hipStream_t s) {
     return TC_OK;
 }
 
+// Workspace of the allocation-free entry point: one array per GPU, held from
+// the library's load to the end of the process and shared by every call on
+// that GPU.  Host code never uses the array's name as an address (it is a
+// host-side stand-in): the device address comes from hipGetSymbolAddress,
+// taken once per device on the first call there, with that device current.
+constexpr int64_t FUSED_SCRATCH_BYTES = (int64_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[FUSED_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {nullptr};
+
+tc_status scratch_address(void **out) {
+    int dev = 0;
+    TC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        TC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return TC_ERR_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TC_OK;
+}
+
 tc_status check_args(const int32_t *src, const int32_t *dst, const int64_t *pair_off,
                      const int64_t *vtx_off, int32_t G, int64_t P, int64_t N, const int64_t *num_edges,
                      const int32_t *status, const tc_fused_tuning *t) {
@@ -595,6 +625,27 @@ tc_status tc_batch_fused(const int32_t *src, const int32_t *dst, const int64_t *
     if (((uintptr_t)workspace & 255) != 0) return TC_ERR_INVALID_ARG;
     return run(src, dst, graph_pair_off, graph_vtx_off, order, num_graphs, num_pairs, num_vertices,
                eu, ev, support, num_edges, tri, triG, num, tc, status, workspace, tuning,
+               (hipStream_t)stream);
+}
+
+int64_t tc_batch_fused_noalloc_max_bytes(void) { return FUSED_SCRATCH_BYTES; }
+
+tc_status tc_batch_fused_noalloc(const int32_t *src, const int32_t *dst,
+                                 const int64_t *graph_pair_off, const int64_t *graph_vtx_off,
+                                 const int32_t *order, int32_t num_graphs, int64_t num_pairs,
+                                 int64_t num_vertices, int32_t *eu, int32_t *ev, uint64_t *support,
+                                 int64_t *num_edges, uint64_t *tri, uint64_t *triG, uint64_t *num,
+                                 double *tc, int32_t *status, const tc_fused_tuning *tuning,
+                                 void *stream) {
+    TC_TRY(check_args(src, dst, graph_pair_off, graph_vtx_off, num_graphs, num_pairs, num_vertices,
+                      num_edges, status, tuning));
+    if (num_graphs == 0) return TC_OK;
+    const int64_t need = tc_batch_fused_workspace_bytes(num_pairs, num_vertices, num_graphs);
+    if (need > FUSED_SCRATCH_BYTES) return TC_ERR_BUDGET;
+    void *ws = nullptr;
+    TC_TRY(scratch_address(&ws));
+    return run(src, dst, graph_pair_off, graph_vtx_off, order, num_graphs, num_pairs, num_vertices,
+               eu, ev, support, num_edges, tri, triG, num, tc, status, ws, tuning,
                (hipStream_t)stream);
 }
 

@@ -79,6 +79,9 @@ _SIGS = {
     "tc_batch_fused_workspace_bytes": (_i64, [_i64, _i64, _i32]),
     "tc_batch_fused": (_st, [_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp,
                              _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(tc_fused_tuning), _vp]),
+    "tc_batch_fused_noalloc_max_bytes": (_i64, []),
+    "tc_batch_fused_noalloc": (_st, [_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp,
+                                     _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(tc_fused_tuning), _vp]),
     "tc_num_graphs": (_i32, [_vp]),
     "tc_batch_edge_offsets": (_st, [_vp, _vp]),
     "tc_compute": (_st, [_vp, _vp]),
@@ -187,6 +190,19 @@ def tc_batch_fused(src, dst, graph_pair_off, graph_vtx_off, order, num_graphs, n
         int(num_vertices), eu, ev, support, num_edges, tri, triG, num, tc, status, workspace,
         int(workspace_bytes), ctypes.byref(tuning) if tuning is not None else None, stream),
         "tc_batch_fused")
+
+
+def tc_batch_fused_noalloc_max_bytes():
+    return int(load().tc_batch_fused_noalloc_max_bytes())
+
+
+def tc_batch_fused_noalloc(src, dst, graph_pair_off, graph_vtx_off, order, num_graphs, num_pairs,
+                           num_vertices, eu, ev, support, num_edges, tri, triG, num, tc, status,
+                           tuning, stream):
+    return _check(load().tc_batch_fused_noalloc(
+        src, dst, graph_pair_off, graph_vtx_off, order, int(num_graphs), int(num_pairs),
+        int(num_vertices), eu, ev, support, num_edges, tri, triG, num, tc, status,
+        ctypes.byref(tuning) if tuning is not None else None, stream), "tc_batch_fused_noalloc")
 
 
 def tc_num_graphs(h):
