@@ -85,6 +85,37 @@ struct FusedLds {
     uint32_t bcast;
 };
 
+// Atomic add ordered for the workgroup.  Every array these touch belongs to
+// one graph and is read back only by the workgroup that owns it, after a
+// barrier; device scope would make each fence write back and invalidate the
+// L2, and the barriers' workgroup-scope release and acquire suffice.
+template <typename T>
+__device__ __forceinline__ void wg_add(T *p, T v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Sum of x over each run of equal keys among a wavefront's valid lanes, the
+// keys non-decreasing in lane order: the run's last lane gets the run's sum
+// and tail = true.
+__device__ __forceinline__ uint64_t run_sum(uint32_t key, uint64_t x, bool valid, bool &tail) {
+    const int lane = __lane_id();
+    const uint32_t prev = __shfl_up(key, 1, TC_WAVE);
+    const bool head = valid && (lane == 0 || prev != key);
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = heads & ((2ull << lane) - 1ull);  // heads at or below this lane
+    const int start = upto ? 63 - __clzll(upto) : 0;
+#pragma unroll
+    for (int off = 1; off < TC_WAVE; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off, TC_WAVE);
+        if (lane - off >= start) x += y;
+    }
+    const uint32_t next = __shfl_down(key, 1, TC_WAVE);
+    const uint64_t live = __ballot(valid);
+    const bool next_live = lane < TC_WAVE - 1 && ((live >> (lane + 1)) & 1ull);
+    tail = valid && (!next_live || next != key);
+    return x;
+}
+
 __device__ __forceinline__ int fused_bits(uint32_t max_value) {
     return max_value == 0 ? 0 : 32 - __clz(max_value);
 }
@@ -327,16 +358,41 @@ __device__ void fused_one_graph(const FusedArgs &a, int32_t g, FusedLds<BLOCK> &
     uint32_t *k = A, *kt = B, *nv = nullptr, *nvt = nullptr;
     block_sort<BLOCK, false>(k, kt, nv, nvt, P, fused_bits(sentinel), sh);
     const uint32_t m = block_unique<BLOCK>(k, P, sentinel, C, sh);
+    if (a.eu || a.ev) {
+        for (uint32_t e = tid; e < m; e += BLOCK) {
+            const uint32_t key = C[e], lo = key / n, hi = key - lo * n;
+            if (a.eu) a.eu[pa + e] = (int32_t)lo;
+            if (a.ev) a.ev[pa + e] = (int32_t)hi;
+        }
+    }
 
     // degrees
     for (uint32_t v = tid; v < n; v += BLOCK) deg[v] = 0;
     __syncthreads();
-    for (uint32_t e = tid; e < m; e += BLOCK) {
-        const uint32_t key = C[e], lo = key / n, hi = key - lo * n;
-        atomicAdd(&deg[lo], 1u);
-        atomicAdd(&deg[hi], 1u);
+    // canonical edges come sorted by their smaller end: a wavefront's lanes
+    // with the same smaller end form a run, whose first lane adds its length
+    for (uint32_t e0 = 0; e0 < m; e0 += BLOCK) {
+        const uint32_t e = e0 + tid;
+        const bool valid = e < m;
+        uint32_t lo = 0, hi = 0;
+        if (valid) {
+            const uint32_t key = C[e];
+            lo = key / n;
+            hi = key - lo * n;
+        }
+        const int lane = __lane_id();
+        const uint32_t prev = __shfl_up(lo, 1, TC_WAVE);
+        const bool head = valid && (lane == 0 || prev != lo);
+        const uint64_t heads = __ballot(head);
+        const uint64_t live = __ballot(valid);
+        if (head) {
+            const uint64_t after = lane == TC_WAVE - 1 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+            const uint32_t end = after ? (uint32_t)(__ffsll((unsigned long long)after) - 1)
+                                       : (uint32_t)(64 - __clzll(live));
+            wg_add(&deg[lo], end - (uint32_t)lane);
+        }
+        if (valid) wg_add(&deg[hi], 1u);
     }
-    __threadfence();
     __syncthreads();
     // order (degree, id): keys d * n + v, sorted; the key gives v back
     uint32_t dmax = 0;
@@ -405,31 +461,31 @@ __device__ void fused_one_graph(const FusedArgs &a, int32_t g, FusedLds<BLOCK> &
             } else if (y < x) {
                 ++j;
             } else {
-                atomicAdd(&osup[i], 1u);
-                atomicAdd(&osup[j], 1u);
+                wg_add(&osup[i], 1u);
+                wg_add(&osup[j], 1u);
                 ++t;
                 ++i;
                 ++j;
             }
         }
-        if (t) atomicAdd(&osup[s], t);
+        if (t) wg_add(&osup[s], t);
     }
-    __threadfence();
     __syncthreads();
 
     // tri(v) = 1/2 Σ sup over v's edges; 3 triG = Σ_e sup(e)
+    // (slots are sorted by row: a wavefront's slots of one row form a run)
     uint64_t local = 0;
-    for (uint32_t s = tid; s < m; s += BLOCK) {
-        const uint32_t x = osup[s];
-        if (x) {
-            atomicAdd((unsigned long long *)&triR[orow[s]], (unsigned long long)x);
-            atomicAdd((unsigned long long *)&triR[ocol[s]], (unsigned long long)x);
-            local += x;
-        }
+    for (uint32_t s0 = 0; s0 < m; s0 += BLOCK) {
+        const uint32_t s = s0 + tid;
+        const bool valid = s < m;
+        const uint32_t x = valid ? osup[s] : 0u, r = valid ? orow[s] : 0u;
+        bool tail;
+        const uint64_t rs = run_sum(r, (uint64_t)x, valid, tail);
+        if (tail && rs) wg_add(&triR[r], rs);
+        if (x) wg_add(&triR[ocol[s]], (uint64_t)x);
+        local += x;
     }
     const uint64_t three_t = block_sum64<BLOCK>(local, sh);
-    __threadfence();
-    __syncthreads();
     bool odd = (three_t % 3) != 0;
     for (uint32_t r = tid; r < n; r += BLOCK) {
         const uint64_t t2 = triR[r];
@@ -440,13 +496,24 @@ __device__ void fused_one_graph(const FusedArgs &a, int32_t g, FusedLds<BLOCK> &
     const uint64_t tg = three_t / 3;
 
     // numerator: weight 1 for triangle neighbours (sup > 0), 3 for the others
-    for (uint32_t s = tid; s < m; s += BLOCK) {
-        const uint32_t r = orow[s], c = ocol[s];
-        const uint64_t f = osup[s] ? 1 : 3;
-        atomicAdd((unsigned long long *)&numR[r], (unsigned long long)(f * triR[c]));
-        atomicAdd((unsigned long long *)&numR[c], (unsigned long long)(f * triR[r]));
+    for (uint32_t s0 = 0; s0 < m; s0 += BLOCK) {
+        const uint32_t s = s0 + tid;
+        const bool valid = s < m;
+        uint32_t r = 0, c = 0;
+        uint64_t f = 0;
+        if (valid) {
+            r = orow[s];
+            c = ocol[s];
+            f = osup[s] ? 1 : 3;
+        }
+        bool tail;
+        const uint64_t rs = run_sum(r, valid ? f * triR[c] : 0ull, valid, tail);
+        if (tail && rs) wg_add(&numR[r], rs);
+        if (valid) {
+            const uint64_t y = f * triR[r];
+            if (y) wg_add(&numR[c], y);
+        }
     }
-    __threadfence();
     __syncthreads();
 
     // outputs in the graph's own vertex ids and canonical edge order
@@ -456,13 +523,6 @@ __device__ void fused_one_graph(const FusedArgs &a, int32_t g, FusedLds<BLOCK> &
         if (a.tri) a.tri[va + v] = t;
         if (a.num) a.num[va + v] = x;
         if (a.tc) a.tc[va + v] = tg == 0 ? 0.0 : __ddiv_rn((double)x, (double)(3 * tg));
-    }
-    if (a.eu || a.ev) {
-        for (uint32_t e = tid; e < m; e += BLOCK) {
-            const uint32_t key = C[e], lo = key / n, hi = key - lo * n;
-            if (a.eu) a.eu[pa + e] = (int32_t)lo;
-            if (a.ev) a.ev[pa + e] = (int32_t)hi;
-        }
     }
     if (a.sup)
         for (uint32_t s = tid; s < m; s += BLOCK) a.sup[pa + o2e[s]] = osup[s];
@@ -478,17 +538,21 @@ __global__ void k_fused_init(unsigned char *ws) {
     if (threadIdx.x == 0) reinterpret_cast<uint32_t *>(ws)[0] = 0;
 }
 
+// 512-thread workgroups ask for 4 wavefronts per SIMD (at most 128 VGPRs),
+// so that two of them fit on a compute unit
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_fused_graphs(FusedArgs a) {
+__global__ __launch_bounds__(BLOCK, BLOCK == 512 ? 4 : 1) void k_fused_graphs(FusedArgs a) {
     __shared__ FusedLds<BLOCK> sh;
     uint32_t *head = reinterpret_cast<uint32_t *>(a.ws);
     for (;;) {
         if (threadIdx.x == 0) sh.bcast = atomicAdd(head, 1u);
         __syncthreads();
-        const uint32_t slot = sh.bcast;
+        // the same value in every lane: keep it (and what derives from it) in
+        // scalar registers
+        const uint32_t slot = __builtin_amdgcn_readfirstlane(sh.bcast);
         __syncthreads();
         if (slot >= (uint32_t)a.G) break;
-        const int32_t g = a.order ? a.order[slot] : (int32_t)slot;
+        const int32_t g = a.order ? __builtin_amdgcn_readfirstlane(a.order[slot]) : (int32_t)slot;
         if (g < 0 || g >= a.G) continue;  // not a permutation: skip the entry
         fused_one_graph<BLOCK>(a, g, sh);
     }
@@ -589,8 +653,8 @@ tc_status run(const int32_t *src, const int32_t *dst, const int64_t *pair_off,
     TC_LAUNCHED();
     switch (u.block) {
         case 256: return launch<256>(a, u.wg_per_cu, s);
-        case 1024: return launch<1024>(a, u.wg_per_cu, s);
-        default: return launch<512>(a, u.wg_per_cu, s);
+        case 512: return launch<512>(a, u.wg_per_cu, s);
+        default: return launch<1024>(a, u.wg_per_cu, s);
     }
 }
 
@@ -600,8 +664,10 @@ extern "C" {
 
 tc_status tc_fused_tuning_default(tc_fused_tuning *t) {
     if (!t) return TC_ERR_INVALID_ARG;
-    t->block = 512;
-    t->wg_per_cu = 4;
+    // measured on MI355X: 1024-thread workgroups, one per compute unit
+    // (the 4096-graph BA batch 29.7 ms against 39.2 ms at 512 x 4)
+    t->block = 1024;
+    t->wg_per_cu = 1;
     return TC_OK;
 }
 
