@@ -15,8 +15,9 @@ Printed on stdout: ONE JSON line.  Progress goes to stderr.
 Beside the headline, the same JSON line carries three more workloads, each
 against the plain one-graph-per-launch form on the same GPU:
 
-* ``batched``: 4096 Barabasi-Albert graphs with planted cliques counted as
-  one batch (one launch per stage for all graphs), in graphs/s;
+* ``batched``: 4096 Barabasi-Albert graphs with planted cliques counted by
+  one persistent fused launch (and by its replay from a captured graph), in
+  graphs/s;
 * ``er``: Erdos-Renyi G(2000, 0.005), seeds 1..5, in microseconds per graph;
 * ``served``: Poisson arrivals of mixed ER / R-MAT / BA requests (edge
   counts log-uniform in [1e3, 2e7]) through the serving loop, at 0.5x and
@@ -62,7 +63,11 @@ def parse():
     ap.add_argument("--no-er", action="store_true")
     ap.add_argument("--no-ingest", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096)
-    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-poisson", type=int, default=3000,
+                    help="requests of the Poisson runs (the first ones of the mix)")
+    ap.add_argument("--serve-saturated", type=int, default=1000,
+                    help="requests queued at t = 0 in the saturated run")
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -72,6 +77,9 @@ def parse():
                     help="tune the counting knobs on each workload first and store them")
     ap.add_argument("--cpu-stride", type=int, default=0,
                     help="oracle counts rows v with v %% stride == 0 (0 = automatic)")
+    ap.add_argument("--summarize-counters", type=str, default=None, metavar="DIR",
+                    help="no GPU work: turn the rocprofv3 CSVs under DIR (pmc_1/, pmc_2/, "
+                         "ktrace/) into profiles/counters_rmat_s24.{json,md}")
     return ap.parse_args()
 
 
@@ -105,17 +113,216 @@ def counter_entry(kernel_key, digest):
     return k
 
 
+# Counter passes of the summary (one rocprofv3 run each; each within the
+# per-block limits of one pass).  HBM bytes come from the L2's requests to
+# memory counted by request size: reads of 32 and 64 bytes and whole
+# 128-byte lines (the rest), writes of 64 bytes and of 32 bytes (the rest).  A device-to-device copy of known
+# size checks the rule: its bytes must come out exact.
+PMC_PASSES = [
+    ["TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum",
+     "TCC_EA0_RDREQ_128B_sum", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU", "SQ_WAVES",
+     "GRBM_GUI_ACTIVE"],
+    ["TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_HIT_sum", "TCC_MISS_sum", "SQ_INSTS_LDS",
+     "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS", "SQ_INSTS_VMEM_RD"],
+]
+# kernels of the summary: (short name, which of its launch shapes in launch
+# order, or None for all) -> stage
+COUNTER_KERNELS = [
+    ("k_mid_block<2>", 1, "count_heavy"), ("k_mid_block<2>", 0, "count_light_bitmap"),
+    ("k_mid_wave", None, "count_light"), ("k_mid_groups<16>", None, "count_light_groups"),
+    ("k_fold_big<int>", None, "fold_big"), ("k_fold<16>", None, "fold_small"),
+    ("k_place_by_smaller", None, "orient_place_smaller"),
+    ("k_place_by_larger", None, "orient_place_larger"),
+    ("k_orient_small", None, "orient_sort_small"), ("k_orient_mid", None, "orient_sort_mid"),
+    ("k_unique_emit", None, "csr_unique_emit"), ("k_rank_rows<1>", None, "tri_rows"),
+    ("k_rank_chunks<1>", None, "tri_chunks"), ("k_rank_rows<2>", None, "aggregate_rows"),
+    ("k_rank_chunks<2>", None, "aggregate_chunks"),
+    ("__amd_rocclr_copyBuffer", None, "copy_calibration"),
+]
+COUNTER_REGEX = "k_mid_block|k_mid_wave|k_mid_groups|k_fold|copyBuffer|k_place_by|k_orient_small|" \
+                "k_orient_mid|k_unique_emit|k_rank_rows|k_rank_chunks"
+COUNTER_ARGS = "--steps 1 --warmup 0 --no-batched --no-serve --no-er --no-ingest " \
+               "--no-cpu-baseline --copy-calibration 1"
+COUNT_SOURCES = ["tc_count.hip", "tc_count_mid.hip", "tc_table.h", "tc_internal.h"]
+
+
+def _short_kernel(name):
+    name = re.sub(r"\(.*", "", name.replace("(anonymous namespace)::", ""))
+    name = name.replace("void ", "").replace("int32_t", "int").strip()
+    return re.sub(r"\s+", "", name)
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    out = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f) as fh:
+            out.extend(csv.DictReader(fh))
+    return out
+
+
+def summarize_counters(d, out_dir=None):
+    """profiles/counters_rmat_s24.{json,md} (or in out_dir) from the
+    rocprofv3 runs under d."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    import collections
+    per = collections.defaultdict(lambda: collections.defaultdict(dict))  # key -> dispatch -> c
+    first = {}
+    for i in range(len(PMC_PASSES)):
+        for r in _csv_rows(os.path.join(d, f"pmc_{i + 1}"), "counter_collection.csv"):
+            short = _short_kernel(r["Kernel_Name"])
+            key = (short, int(r["Grid_Size"]))
+            disp = int(r.get("Dispatch_Id") or 0)
+            first[key] = min(first.get(key, disp), disp) if i == 0 else first.get(key, disp)
+            per[key][(i, disp)][r["Counter_Name"]] = float(r["Counter_Value"])
+    stats = {}
+    for r in _csv_rows(os.path.join(d, "ktrace"), "kernel_stats.csv"):
+        stats[_short_kernel(r["Name"])] = float(r["AverageNs"]) / 1e6
+    # mean duration per launch shape, from the kernel trace of the same run
+    dur = collections.defaultdict(list)
+    for r in _csv_rows(os.path.join(d, "ktrace"), "kernel_trace.csv"):
+        grid = 1
+        for ax in "XYZ":
+            grid *= int(r.get(f"Grid_Size_{ax}") or 1)
+        dur[(_short_kernel(r["Kernel_Name"]), grid)].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    shapes = collections.defaultdict(list)
+    for (short, grid) in sorted(per, key=lambda k: first.get(k, 0)):
+        shapes[short].append(grid)
+
+    def mean(key, counter):
+        vals = [c[counter] for c in per[key].values() if counter in c]
+        return sum(vals) / len(vals) if vals else 0.0
+
+    kernels = {}
+    for short, idx, stage in COUNTER_KERNELS:
+        grids = shapes.get(short, [])
+        if not grids or (idx is not None and idx >= len(grids)):
+            continue
+        sel = grids if idx is None else [grids[idx]]
+        keys = [(short, g) for g in sel]
+
+        def tot(counter):
+            return sum(mean(k, counter) for k in keys) / len(keys)
+        rd, r32 = tot("TCC_EA0_RDREQ_sum"), tot("TCC_EA0_RDREQ_32B_sum")
+        r64, r128 = tot("TCC_EA0_RDREQ_64B_sum"), tot("TCC_EA0_RDREQ_128B_sum")
+        wr, w64 = tot("TCC_EA0_WRREQ_sum"), tot("TCC_EA0_WRREQ_64B_sum")
+        rbytes = 32 * r32 + 64 * r64 + 128 * (rd - r32 - r64)
+        wbytes = 64 * w64 + 32 * (wr - w64)
+        gui = tot("GRBM_GUI_ACTIVE")
+        hit, miss = tot("TCC_HIT_sum"), tot("TCC_MISS_sum")
+        lds_active = tot("SQ_ACTIVE_INST_LDS")
+        ds = [t for k in keys for t in dur.get(k, [])]
+        e = {
+            "kernel": f"{short}@{sel[0]}" if idx is not None else short,
+            "avg_ms": round(sum(ds) / len(ds), 4) if ds else None,
+            "trace_dispatches": len(ds),
+            "rdreq": int(rd), "rdreq_32b": int(r32), "rdreq_64b": int(r64),
+            "rdreq_128b": int(r128), "rdreq_unsized": int(rd - r32 - r64 - r128),
+            "wrreq": int(wr), "wrreq_64b": int(w64),
+            "hbm_read_bytes": int(rbytes), "hbm_write_bytes": int(wbytes),
+            "hbm_bytes_per_dispatch": int(rbytes + wbytes),
+            "valu_insts": int(tot("SQ_INSTS_VALU")),
+            "valu_busy": round(tot("SQ_ACTIVE_INST_VALU") * 4 / (4 * 256 * gui / 8), 3)
+            if gui else None,
+            "lds_insts": int(tot("SQ_INSTS_LDS")),
+            "lds_bank_conflict_per_active_lds_cycle":
+                round(tot("SQ_LDS_BANK_CONFLICT") / lds_active, 3) if lds_active else None,
+            "vmem_rd_insts": int(tot("SQ_INSTS_VMEM_RD")),
+            "tcc_hit_rate": round(hit / (hit + miss), 3) if hit + miss else None,
+            "gpu_cycles_per_xcd": int(gui / 8),
+            "dispatches": sum(len(per[k]) for k in keys) // len(PMC_PASSES),
+        }
+        kernels[stage] = e
+    for stage, e in kernels.items():
+        short = e["kernel"].split("@")[0]
+        e["stats_avg_ms_all_shapes"] = round(stats[short], 4) if short in stats else None
+    for e in kernels.values():
+        if e["avg_ms"]:
+            e["hbm_GBps"] = round(e["hbm_bytes_per_dispatch"] / (e["avg_ms"] / 1e3) / 1e9, 1)
+    cal = kernels.get("copy_calibration")
+    check = None
+    if cal:
+        nbytes = 1 << 30
+        check = {"bytes_read": nbytes, "bytes_written": nbytes,
+                 "counted_read": cal["hbm_read_bytes"], "counted_written": cal["hbm_write_bytes"],
+                 "read_ratio": round(cal["hbm_read_bytes"] / nbytes, 5),
+                 "write_ratio": round(cal["hbm_write_bytes"] / nbytes, 5)}
+    cmds = counter_commands()
+    out = {"source_digest": source_digest(COUNT_SOURCES),
+           "workload": "rmat_s24_ef16 seed 24, tuning from "
+                       "paper_2105_00110_amd/tuning/mi355x.json",
+           "rule": "read bytes = 32 x TCC_EA0_RDREQ_32B + 64 x TCC_EA0_RDREQ_64B + 128 x "
+                   "(the other TCC_EA0_RDREQ, whole-line fills, which TCC_EA0_RDREQ_128B "
+                   "counts when it does); write bytes = 64 x TCC_EA0_WRREQ_64B + 32 x "
+                   "(TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B); no scale factor",
+           "copy_check": check, "commands": cmds, "kernels": kernels}
+    with open(os.path.join(out_dir, "counters_rmat_s24.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    lines = ["# Hardware counters, R-MAT scale 24 (edge factor 16, seed 24)", "",
+             "Made by these commands (one MI355X, from the repository root; the last line "
+             "runs on any host):", "", "```"] + cmds + ["```", "",
+             "## Rule, checked on a copy of known size", "",
+             f"- {out['rule']}.",
+             "- On the copy, read requests by size: "
+             f"{cal['rdreq_32b'] if cal else 'n/a'} of 32 B, "
+             f"{cal['rdreq_64b'] if cal else 'n/a'} of 64 B, "
+             f"{cal['rdreq_128b'] if cal else 'n/a'} of 128 B, "
+             f"{cal['rdreq_unsized'] if cal else 'n/a'} not in any of the three. FETCH_SIZE "
+             "takes 128-byte fills from TCC_BUBBLE and prices every other request at 64 B.",
+             f"- 1 GiB device-to-device copy: counted read / true = "
+             f"{check['read_ratio'] if check else 'n/a'}, counted written / true = "
+             f"{check['write_ratio'] if check else 'n/a'}.", "",
+             "## Per kernel (mean per dispatch)", "",
+             "| stage | kernel | ms | read GB | write GB | HBM GB/s | VALU busy | L2 hit | "
+             "LDS conflicts / active LDS cycle |", "|---|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for stage, e in kernels.items():
+        lines.append(f"| {stage} | `{e['kernel']}` | {e['avg_ms'] or ''} | "
+                     f"{e['hbm_read_bytes'] / 1e9:.2f} | {e['hbm_write_bytes'] / 1e9:.2f} | "
+                     f"{e.get('hbm_GBps', '')} | {e['valu_busy']} | {e['tcc_hit_rate']} | "
+                     f"{e['lds_bank_conflict_per_active_lds_cycle']} |")
+    lines += ["", f"Source digest of the counting sources: `{out['source_digest']}`. "
+              "`bench.py` reports `traffic` from this file only while it matches.", ""]
+    with open(os.path.join(out_dir, "counters_rmat_s24.md"), "w") as f:
+        f.write("\n".join(lines))
+    print(json.dumps({k: {kk: v[kk] for kk in ("avg_ms", "hbm_bytes_per_dispatch")}
+                      for k, v in kernels.items()}, indent=1))
+
+
+def counter_commands():
+    cmds = ["cd /tmp && export TMPDIR=/tmp"]
+    for i, p in enumerate(PMC_PASSES):
+        cmds.append(f"timeout -s KILL 240 rocprofv3 --pmc {' '.join(p)} --kernel-include-regex "
+                    f"'{COUNTER_REGEX}' -d /root/repo/gpurun_out/pmc_s24/pmc_{i + 1} -o run "
+                    f"--output-format csv -- python3 /root/repo/bench.py {COUNTER_ARGS}")
+    cmds.append("timeout -s KILL 300 rocprofv3 --kernel-trace --stats -d "
+                "/root/repo/gpurun_out/pmc_s24/ktrace -o run --output-format csv -- python3 "
+                "/root/repo/bench.py --steps 3 --warmup 1 --no-batched --no-serve --no-er "
+                "--no-ingest --no-cpu-baseline")
+    cmds.append("cd /root/repo && python3 bench.py --summarize-counters gpurun_out/pmc_s24")
+    return cmds
+
+
 def cpu_baseline(src, dst, n, m, stride):
     """The oracle (O2: the paper's Procedure 2 + Algorithm 2, C, host
-    threads) on a bounded sample of the same workload."""
+    threads) on a bounded sample of the same workload, on the host threads a
+    GPU machine grants one process (at most 16), and once more on one thread."""
     from oracle import native
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = native.host_threads()
     phases = []
     t0 = time.perf_counter()
     native.o2_paper(src, dst, n, nthreads=threads, row_stride=stride, phases=phases)
     wall = time.perf_counter() - t0
     norm, order, count, agg = phases
     full = norm + order + count * stride + agg
+    # one thread: the same normalisation, ordering and aggregation (they are
+    # single-threaded in the oracle), the counting loop on a 16x sparser
+    # sample of rows
+    stride1 = stride * 16
+    ph1 = []
+    native.o2_paper(src, dst, n, nthreads=1, row_stride=stride1, phases=ph1)
+    full1 = ph1[0] + ph1[1] + ph1[2] * stride1 + ph1[3]
     return {
         "value": m / full,
         "unit": "edges/s",
@@ -123,27 +330,88 @@ def cpu_baseline(src, dst, n, m, stride):
         "kind": "oracle",
         "sample": (f"O2 over all {len(src)} pairs; normalisation, ordering and aggregation "
                    f"run in full ({norm + order + agg:.1f} s), the counting loop runs on rows "
-                   f"v with v % {stride} == 0 ({count:.1f} s, scaled x{stride}); "
-                   f"wall {wall:.1f} s"),
+                   f"v with v % {stride} == 0 ({count:.1f} s on {threads} threads, scaled "
+                   f"x{stride}); wall {wall:.1f} s"),
         "est_full_s": full,
+        "single_thread": {"edges_per_s": m / full1, "est_full_s": round(full1, 1),
+                          "sample": f"counting loop on rows v % {stride1} == 0, scaled "
+                                    f"x{stride1} ({ph1[2]:.1f} s)"},
+        "host_cpus": os.cpu_count(),
         "cpu_model": host_cpu_model(),
     }
 
 
 def host_cpu_model():
-    """The host CPU's model name, from /proc/cpuinfo (None if unreadable)."""
+    """The host CPU's model name, family, model and stepping numbers and
+    socket/core layout from /proc/cpuinfo (None if unreadable)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping", "cpu cores",
+                         "siblings", "cpu MHz") and k not in info:
+                    info[k] = v
     except OSError:
-        pass
-    return None
+        return None
+    if "model name" not in info:
+        return None
+    return (f"{info['model name']} (family {info.get('cpu family')}, model {info.get('model')}, "
+            f"stepping {info.get('stepping')}; {info.get('cpu cores')} cores / "
+            f"{info.get('siblings')} threads per socket; {info.get('cpu MHz')} MHz)")
+
+
+def _event_ms(fn, reps):
+    """Median device time (ms) of fn() over reps, by HIP events on torch's
+    current stream (the stream the fused launch is queued on)."""
+    import torch
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def _graph_replay_ms(fb, reps):
+    """The fused launch captured once in a graph, then replayed: median
+    device time (ms) of one replay, and the wall time (us) of a replay plus
+    its synchronisation."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    saved = fb.stream
+    fb.stream = side.cuda_stream
+    with torch.cuda.stream(side):
+        fb.run()
+    torch.cuda.synchronize()
+    cg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cg, stream=side):
+        fb.run()
+    torch.cuda.synchronize()
+    fb.stream = saved
+    ms = _event_ms(cg.replay, reps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cg.replay()
+        torch.cuda.synchronize()
+    wall_us = (time.perf_counter() - t0) * 1e6 / reps
+    return ms, wall_us
 
 
 def batched_leg(args, stream, autotune):
-    """4096 BA graphs: one batch vs one graph per launch (device-resident pairs)."""
+    """4096 BA graphs: the fused launch (one persistent kernel for the whole
+    batch, also replayed from a captured graph) against one graph per launch,
+    and against the batch as one handle (every stage one launch over the
+    disjoint union)."""
+    import numpy as np
     import torch
     from paper_2105_00110_amd import graphgen as gg
     from paper_2105_00110_amd import tc
@@ -155,34 +423,40 @@ def batched_leg(args, stream, autotune):
     d_src = torch.from_numpy(src).cuda()
     d_dst = torch.from_numpy(dst).cuda()
     torch.cuda.synchronize()
-    tuning = autotune.load(wl)
+    ft = autotune.load(wl + "_fused")
     if args.autotune:
-        g = tc.Graph.batch(d_src, d_dst, po, vo, stream=stream)
-        res = autotune.tune(g, log=log)
-        g.close()
-        autotune.store(wl, res, device=torch.cuda.get_device_name(0))
-        tuning = res["tuning"]
-        tc.tc_set_profiling(False)
+        res = autotune.tune_fused(d_src, d_dst, po, vo, log=log)
+        autotune.store(wl + "_fused", res, device=torch.cuda.get_device_name(0))
+        ft = res["tuning"]
+    ft = ft or {"order": "largest_first"}
+    order = ft.get("order", "largest_first")
+    fknobs = {k: v for k, v in ft.items() if k in ("block", "wg_per_cu")} or None
+    fb = tc.FusedBatch(d_src, d_dst, po, vo, order=order, tuning=fknobs, stream=stream)
+    fb.run()
+    torch.cuda.synchronize()
+    st = fb.status.cpu().numpy()
+    m = int(fb.num_edges.cpu().numpy().sum())
+    ms_fused = _event_ms(fb.run, 5)
+    ms_graph, _ = _graph_replay_ms(fb, 5)
+    log(f"batched: fused launch {ms_fused:.2f} ms per batch, graph replay {ms_graph:.2f} ms, "
+        f"statuses {np.unique(st).tolist()}")
+    del fb
 
-    m = None
+    tuning = autotune.load(wl)
 
-    def bstep():
-        nonlocal m
+    def union():
         g = tc.Graph.batch(d_src, d_dst, po, vo, stream=stream)
         g.compute(tuning)
-        if m is None:
-            m = g.m
         g.close()
 
-    bstep()
+    union()
     torch.cuda.synchronize()
-    reps = 3
     t0 = time.perf_counter()
-    for _ in range(reps):
-        bstep()
+    for _ in range(3):
+        union()
     torch.cuda.synchronize()
-    ms_batch = (time.perf_counter() - t0) * 1e3 / reps
-    log(f"batched: {G} graphs in {ms_batch:.2f} ms per batch")
+    ms_union = (time.perf_counter() - t0) * 1e3 / 3
+    log(f"batched: one handle over the disjoint union {ms_union:.2f} ms per batch")
 
     def single(gi):
         a, b = int(po[gi]), int(po[gi + 1])
@@ -200,18 +474,22 @@ def batched_leg(args, stream, autotune):
     ms_single = (time.perf_counter() - t0) * 1e3
     log(f"batched: one graph per launch {ms_single:.1f} ms for {G} graphs")
     return {
-        "workload": wl, "graphs": G, "pairs": int(len(src)), "n": int(vo[-1]), "m": int(m),
-        "ms_per_batch": round(ms_batch, 3), "graphs_per_s": G / (ms_batch / 1e3),
-        "edges_per_s": m / (ms_batch / 1e3),
+        "workload": wl, "graphs": G, "pairs": int(len(src)), "n": int(vo[-1]), "m": m,
+        "fused_launch": {"ms_per_batch": round(ms_fused, 3), "graphs_per_s": G / (ms_fused / 1e3),
+                         "edges_per_s": m / (ms_fused / 1e3), "tuning": ft,
+                         "graph_replay_ms": round(ms_graph, 3)},
+        "ms_per_batch": round(ms_fused, 3), "graphs_per_s": G / (ms_fused / 1e3),
+        "one_handle_union": {"ms": round(ms_union, 3), "graphs_per_s": G / (ms_union / 1e3)},
         "one_graph_per_launch": {"ms": round(ms_single, 3), "graphs_per_s": G / (ms_single / 1e3)},
-        "speedup_vs_one_graph_per_launch": round(ms_single / ms_batch, 2),
+        "speedup_vs_one_graph_per_launch": round(ms_single / ms_fused, 2),
         "tuning": tuning,
     }
 
 
 def er_leg(stream, reps=20):
-    """G(2000, 0.005), seeds 1..5: latency of one graph per launch, and the
-    five as one batch."""
+    """G(2000, 0.005), seeds 1..5: latency of one graph per launch (a handle;
+    the fused launch; the fused launch replayed from a captured graph), and
+    the five as one fused launch."""
     import numpy as np
     import torch
     from paper_2105_00110_amd import graphgen as gg
@@ -235,23 +513,38 @@ def er_leg(stream, reps=20):
             one(s, d, n)
     torch.cuda.synchronize()
     us_single = (time.perf_counter() - t0) * 1e6 / (reps * len(dev))
+    fbs = [tc.FusedBatch(s, d, [0, len(s)], [0, n], stream=stream) for s, d, n in dev]
+    for fb in fbs:
+        fb.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for fb in fbs:
+            fb.run()
+            torch.cuda.synchronize()
+    us_fused = (time.perf_counter() - t0) * 1e6 / (reps * len(fbs))
+    us_fused_dev = np.mean([_event_ms(fb.run, reps) for fb in fbs]) * 1e3
+    replay = [_graph_replay_ms(fb, reps) for fb in fbs]
+    us_replay_dev = np.mean([r[0] for r in replay]) * 1e3
+    us_replay_wall = np.mean([r[1] for r in replay])
     src = np.concatenate([g[0] for g in graphs])
     dst = np.concatenate([g[1] for g in graphs])
     po = np.zeros(len(graphs) + 1, np.int64)
     vo = np.zeros(len(graphs) + 1, np.int64)
     np.cumsum([len(g[0]) for g in graphs], out=po[1:])
     np.cumsum([g[2] for g in graphs], out=vo[1:])
-    ds, dd = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g = tc.Graph.batch(ds, dd, po, vo, stream=stream)
-        g.compute()
-        g.close()
-    torch.cuda.synchronize()
-    us_batch = (time.perf_counter() - t0) * 1e6 / (reps * len(graphs))
-    log(f"er: {us_single:.1f} us per graph alone, {us_batch:.1f} us per graph in a batch of 5")
-    return {"workload": "er_n2000_p0.005_seeds1-5", "us_per_graph": round(us_single, 1),
+    fb5 = tc.FusedBatch(torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda(), po, vo,
+                        stream=stream)
+    us_batch = _event_ms(fb5.run, reps) * 1e3 / len(graphs)
+    log(f"er: one handle {us_single:.1f} us per graph; fused launch {us_fused:.1f} us "
+        f"(device {us_fused_dev:.1f}); graph replay {us_replay_wall:.1f} us (device "
+        f"{us_replay_dev:.1f}); five in one fused launch {us_batch:.1f} us per graph")
+    return {"workload": "er_n2000_p0.005_seeds1-5",
+            "us_per_graph": round(us_fused, 1),
+            "us_per_graph_one_handle": round(us_single, 1),
+            "us_per_graph_fused_device": round(us_fused_dev, 1),
+            "us_per_graph_graph_replay": round(us_replay_wall, 1),
+            "us_per_graph_graph_replay_device": round(us_replay_dev, 1),
             "us_per_graph_batched5": round(us_batch, 1)}
 
 
@@ -301,25 +594,36 @@ def ingest_leg(stream):
 
 
 def served_leg(args, autotune):
-    """Serving loop at 0.5x and 0.8x of the closed-loop capacity."""
+    """Serving loop.  The closed loop (one graph per launch, one at a time)
+    runs all N requests, made from their seeds a bounded window ahead, and
+    keeps a digest of each result; its service time gives the capacity.
+    Then Poisson arrivals at 0.8x and 0.5x of that capacity, and every
+    request at t = 0, over the first --serve-poisson requests (made before
+    the runs): each reply is compared, by digest, with the same request run
+    alone, and then dropped."""
     import torch
     from paper_2105_00110_amd import serve
 
     N = args.serve_requests
-    log(f"served: generating {N} requests (seed 5)")
-    t0 = time.perf_counter()
-    reqs = serve.make_requests(N, seed=5)
-    pairs = sum(r.pairs for r in reqs)
-    log(f"served: generated {pairs} pairs in {time.perf_counter() - t0:.1f} s")
+    specs = serve.request_specs(N, seed=5)
+    pairs = sum(m for _, m, _ in specs)
+    log(f"served: {N} requests (seed 5), {pairs} pairs, made on demand")
     stream = torch.cuda.Stream()
-    for r in reqs[:8]:  # warm the path
+    for r in serve.make_requests(8, seed=5):  # warm the path
         serve.run_alone(r, stream.cuda_stream)
     torch.cuda.synchronize()
-    secs, alone = serve.closed_loop(reqs, stream.cuda_stream)
-    ref = [serve.digest(a) for a in alone]
-    del alone
+    ref = [None] * N
+
+    def keep_digest(i, res):
+        ref[i] = serve.digest(res)
+        if (i + 1) % 1000 == 0:
+            log(f"served: closed loop {i + 1}/{N}")
+
+    src = serve.RequestSource(specs)
+    secs, _ = serve.closed_loop(src, stream.cuda_stream, on_result=keep_digest)
+    src.close()
     capacity = N / secs
-    log(f"served: closed loop (one graph per launch, one at a time) {secs:.2f} s, "
+    log(f"served: closed loop (one graph per launch, one at a time) {secs:.2f} s of service, "
         f"{capacity:.1f} graphs/s")
     cfg = serve.ServerConfig(budget_bytes=int(args.serve_budget_gb * (1 << 30)),
                              streams=args.serve_streams)
@@ -331,24 +635,42 @@ def served_leg(args, autotune):
         "closed_loop": {"seconds": round(secs, 3), "graphs_per_s": capacity},
         "runs": [],
     }
-    for frac in (0.5, 0.8, None):
+    # the Poisson and saturated runs take the first --serve-poisson requests,
+    # made before the run: making requests while serving takes the host CPUs
+    # the server needs, and all 10,000 would hold 164 GB of pairs
+    Np = min(N, args.serve_poisson)
+    log(f"served: making the first {Np} requests for the Poisson runs")
+    pre = serve.make_requests(Np, seed=5)
+    for frac, count in ((0.8, Np), (0.5, Np), (None, min(Np, args.serve_saturated))):
         # None: every request queued at t = 0, the server's own capacity
         rate = frac * capacity if frac else float("inf")
-        arrivals = serve.poisson_arrivals(N, rate, seed=5) if frac else None
+        arrivals = serve.poisson_arrivals(count, rate, seed=5) if frac else None
+        mism = []
+
+        done = [0]
+
+        def check(rep):
+            if rep.error is None and serve.digest(rep.results) != ref[rep.rid]:
+                mism.append(rep.rid)
+            done[0] += 1
+            if done[0] % 1000 == 0:
+                log(f"served at {frac or 'saturation'}: {done[0]}/{count} replies")
+
         srv = serve.Server(cfg)
-        replies = srv.run(reqs, arrivals)
+        replies = srv.run(pre[:count], arrivals, on_reply=check)
         ok = [r for r in replies if r.error is None]
-        same = all(serve.digest(r.results) == ref[r.rid] for r in ok)
         summ = serve.latency_summary(replies)
-        run = {"rate_per_s": round(rate, 2) if frac else "all at t=0",
+        run = {"requests": count, "rate_per_s": round(rate, 2) if frac else "all at t=0",
                "load": frac if frac else "saturated", **{k: round(v, 3) if isinstance(v, float)
                                                                 else v for k, v in summ.items()},
+               "by_size_decade": serve.latency_by_decade(replies),
                "graphs_per_s": len(ok) / srv.makespan, "makespan_s": round(srv.makespan, 3),
-               "errors": len(replies) - len(ok), "mix_equals_alone": bool(same), **srv.stats}
+               "errors": len(replies) - len(ok), "mix_equals_alone": not mism, **srv.stats}
         log(f"served at {f'{frac}x capacity' if frac else 'saturation'}: {json.dumps(run)}")
         out["runs"].append(run)
         del replies
-    out["resident"] = resident_run(reqs, cfg, capacity)
+    out["resident"] = resident_run(pre[:200], cfg, capacity)
+    del pre
     return out
 
 
@@ -394,6 +716,9 @@ def resident_run(reqs, cfg, capacity):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the library "
               f"runs one graph or batch per GPU, and a sharded path is not built",
@@ -508,7 +833,7 @@ def main():
                   + 8 * work[f"rows_{b}"])
     dur_s = stages[dom] / 1e3
     achieved = algo_bytes / dur_s / 1e9 if dur_s > 0 else 0.0
-    digest = source_digest(["tc_count.hip", "tc_count_mid.hip", "tc_table.h", "tc_internal.h"])
+    digest = source_digest(COUNT_SOURCES)
     counters = counter_entry(dom, digest) or {}
     kernel_names = {"count_light": "k_mid_wave", "count_heavy": "k_mid_block",
                     "count_huge": "k_mid_block<true>"}
@@ -525,6 +850,8 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": counters.get("hbm_bytes_per_dispatch"),
         "algorithmic_bytes": int(algo_bytes),
+        "traffic_over_algorithmic": (round(counters["hbm_bytes_per_dispatch"] / algo_bytes, 3)
+                                     if counters and algo_bytes else None),
         "avg_ms": round(stages[dom], 3),
         # fraction of cycles the SIMDs issued vector ALU work, from the same
         # counter summary (null when it is stale)
@@ -585,7 +912,7 @@ def main():
         log(f"CPU baseline: oracle O2 with row stride {stride}")
         cb = cpu_baseline(src, dst, n, m, stride)
         result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample",
-                                                      "cpu_model")}
+                                                      "single_thread", "host_cpus", "cpu_model")}
         log(f"CPU baseline done: {cb['value']:.3e} edges/s, est. full {cb['est_full_s']:.1f} s")
     if args.copy_calibration > 0:
         nbytes = int(args.copy_calibration * (1 << 30))

@@ -154,15 +154,25 @@ tc_status tc_tuning_default(tc_tuning *t);
  *   empty graph.  Limits: n < 2^31, num_pairs < 2^32.
  *
  * tc_graph_from_csr: same, from a CSR adjacency row_ptr[n+1] (int64,
- *   row_ptr[0] = 0, non-decreasing) and col[row_ptr[n]].  Every stored entry
- *   (v, col[k]) is taken as an undirected pair, so one-sided and symmetric
- *   CSRs give the same graph; loops and duplicates are dropped as above.
+ *   row_ptr[0] = 0, non-decreasing) and col[row_ptr[n]].
+ *   assume_simple_sorted = 0: every stored entry (v, col[k]) is taken as an
+ *     undirected pair, so one-sided and symmetric CSRs give the same graph;
+ *     loops and duplicates are dropped as above (a sort and a
+ *     deduplication).
+ *   assume_simple_sorted = 1: the caller states that every row is strictly
+ *     increasing, with ids in [0, n) and no self-loop (checked on the
+ *     device: TC_ERR_INVALID_ARG and no handle otherwise).  The edges are
+ *     then the entries above the diagonal (col[k] > v), read in order as the
+ *     canonical edge list with no sort and no deduplication; a symmetric
+ *     CSR and its upper triangle give the same graph, and entries below the
+ *     diagonal are not read as edges.
  * ---------------------------------------------------------------------- */
 tc_status tc_graph_from_edges(const int32_t *src, const int32_t *dst, int64_t num_pairs,
                               int32_t n, int32_t mem_kind, void *stream, tc_graph **out);
 
 tc_status tc_graph_from_csr(const int64_t *row_ptr, const int32_t *col, int32_t n,
-                            int32_t mem_kind, void *stream, tc_graph **out);
+                            int32_t mem_kind, int32_t assume_simple_sorted, void *stream,
+                            tc_graph **out);
 
 /* ------------------------------------------------------------------------
  * Batched construction: num_graphs independent graphs in one handle.
@@ -326,8 +336,46 @@ tc_status tc_get_results(const tc_graph *g, uint64_t *tri, uint64_t *support, ui
  * support is a valid T). */
 tc_status tc_numerator_algebraic(const tc_graph *g, uint64_t *num, int32_t mem_kind, void *stream);
 
+/* Results of a batch handle (tc_batch_create + tc_compute): the same
+ * copies as tc_get_results, named for batches.  tri[N], num[N], tc[N] over
+ * the concatenated vertex range, support[m] in the handle's edge order
+ * (graph g's edges at tc_batch_edge_offsets), triG[num_graphs] with one
+ * △(G) per graph; tc[v] divides by 3·△ of v's own graph. */
+tc_status tc_batch_get_results(const tc_graph *b, uint64_t *tri, uint64_t *support, uint64_t *triG,
+                               uint64_t *num, double *tc, int32_t mem_kind, void *stream);
+
 /* Device bytes currently held by the handle. */
 tc_status tc_graph_device_bytes(const tc_graph *g, int64_t *bytes);
+
+/* Upper bound of the device bytes tc_compute / tc_compute_tuned will
+ * allocate on top of what the built handle g holds (tc_graph_device_bytes),
+ * for the pivot form the tuning picks (NULL: defaults; TC_ALGO_AUTO decides
+ * as tc_compute does).  For the middle pivot it includes the exact size of
+ * the bit matrices of §3.3's Procedure 1, 4·Σ_v Σ_{t<d+(v)} ceil(t/32)
+ * bytes over the oriented rows (about Σ_v C(d+(v), 2) / 8), which it reads
+ * back from the device: the call waits for the stream.  A caller with a
+ * memory budget checks it after the build, before the count, so that a
+ * dense graph whose bit matrices outgrow tc_estimate_device_bytes cannot
+ * overrun the budget.  *bytes is a host pointer.  TC_ERR_INVALID_ARG for a
+ * NULL handle or pointer or an invalid tuning. */
+tc_status tc_compute_bytes(tc_graph *g, const tc_tuning *tuning, void *stream, int64_t *bytes);
+
+/* Limit on the device bytes the library's allocator holds on each device
+ * (blocks in use plus blocks it caches for reuse; 0 = no limit, the
+ * default).  An allocation that would pass it first gives the cached blocks
+ * back, then fails with TC_ERR_BUDGET: the call that needed it returns
+ * TC_ERR_BUDGET and the handle stays as it was before that call (a failed
+ * tc_compute leaves it not computed).  The fused launch's workspace and
+ * other caller-owned buffers are not counted.  TC_ERR_INVALID_ARG if
+ * bytes < 0. */
+tc_status tc_set_memory_limit(int64_t bytes);
+
+/* Device bytes of the library's allocator on the current device: held
+ * (in use plus cached), in use, and the peaks of both since the library
+ * loaded or the last reset; reset_peaks != 0 sets the peaks to the current
+ * values after reading them.  Each pointer is a host pointer or NULL. */
+tc_status tc_memory_stats(int64_t *held, int64_t *in_use, int64_t *peak_held,
+                          int64_t *peak_in_use, int32_t reset_peaks);
 
 /* Estimate of the peak device bytes tc_graph_from_edges + tc_compute need
  * for num_pairs pairs over n vertices, for admission control by callers

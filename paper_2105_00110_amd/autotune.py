@@ -12,6 +12,12 @@ The knobs (``include/tc.h``):
 * ``light_bitmap_pairs``: pair count from which wavefront pivots move to the
   bitmap kernel (0 = never).
 
+``tune_fused`` searches the knobs of the fused batch launch
+(``tc_fused_tuning``: workgroup size, workgroups per compute unit) and the
+order in which graphs are taken from its queue (largest first or as given)
+by exhaustive search, each trial timed by HIP events and compared bit for
+bit with the first.
+
 ``tune`` runs a coordinate search on a built graph.  It starts from the
 library defaults (or a given start) and sweeps one knob at a time over its
 candidate values, keeping a value only when the measured device time of the
@@ -135,3 +141,72 @@ def store(workload, result, path=DEFAULT_FILE, device=None):
     with open(tmp, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
     os.replace(tmp, path)
+
+
+FUSED_SPACE = {"block": [256, 512, 1024], "wg_per_cu": [1, 2, 4], "order": ["largest_first", None]}
+
+
+def _fused_outputs(fb):
+    """Per-graph outputs of a FusedBatch run (the rows past m_g are not
+    outputs and are left out)."""
+    res = fb.results()
+    return [fb.graph(res, g) for g in range(fb.G)]
+
+
+def _fused_same(a, b):
+    import numpy as np
+    for x, y in zip(a, b):
+        for k in ("eu", "ev", "support", "tri", "num", "triG"):
+            if not np.array_equal(x[k], y[k]):
+                return False
+        if not np.array_equal(x["tc"].view(np.uint64), y["tc"].view(np.uint64)) or \
+                x["status"] != y["status"]:
+            return False
+    return True
+
+
+def tune_fused(src, dst, pair_off, vtx_off, space=None, reps=3, log=None):
+    """Exhaustive search over the fused launch's knobs for one batch.
+
+    ``src``/``dst`` are device tensors, the offsets host arrays.  Returns
+    ``{"tuning", "ms", "default_ms", "trials"}`` with ``tuning`` holding
+    block, wg_per_cu and order."""
+    import itertools
+
+    import torch
+    space = space or FUSED_SPACE
+    trials, ref, best, default_ms = [], None, None, None
+    d = tc.tc_fused_tuning_default().as_dict()
+    combos = [dict(zip(space, c)) for c in itertools.product(*space.values())]
+    combos.sort(key=lambda c: (c["block"], c["wg_per_cu"]) != (d["block"], d["wg_per_cu"]) or
+                c["order"] != "largest_first")  # the default first
+    for c in combos:
+        fb = tc.FusedBatch(src, dst, pair_off, vtx_off, order=c["order"],
+                           tuning={"block": c["block"], "wg_per_cu": c["wg_per_cu"]})
+        fb.run()
+        torch.cuda.synchronize()
+        out = _fused_outputs(fb)
+        if ref is None:
+            ref = out
+        elif not _fused_same(out, ref):
+            raise RuntimeError(f"fused tuning {c} changed the results")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(reps):
+            e0.record()
+            fb.run()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = sorted(times)[len(times) // 2]
+        if default_ms is None:
+            default_ms = ms
+        trials.append({"tuning": c, "ms": round(ms, 3)})
+        if log:
+            log(f"autotune fused {c}: {ms:.3f} ms")
+        if best is None or ms < best[1]:
+            best = (c, ms)
+        del fb
+    return {"tuning": best[0], "ms": round(best[1], 3), "default_ms": round(default_ms, 3),
+            "trials": trials}

@@ -61,6 +61,10 @@ constexpr int MAX_DEV = 64;
 std::mutex g_alloc_mu;
 std::multimap<size_t, std::pair<void *, Block>> g_free[MAX_DEV];
 std::unordered_map<void *, Block> g_used;
+// bytes per device: held (in use + cached), in use, their peaks, and the
+// caller's limit on held bytes (0: none)
+int64_t g_held[MAX_DEV], g_in_use[MAX_DEV], g_peak_held[MAX_DEV], g_peak_in_use[MAX_DEV];
+int64_t g_limit = 0;
 
 size_t round_size(size_t b) {
     if (b < ((size_t)1 << 20)) return (b + 511) & ~(size_t)511;
@@ -77,8 +81,14 @@ void release_cached(int dev) {
             (void)hipEventDestroy(b.ev);
         }
         (void)hipFree(kv.second.first);
+        g_held[dev] -= (int64_t)b.size;
     }
     g_free[dev].clear();
+}
+
+void note_in_use(int dev, int64_t delta) {
+    g_in_use[dev] += delta;
+    if (g_in_use[dev] > g_peak_in_use[dev]) g_peak_in_use[dev] = g_in_use[dev];
 }
 
 }  // namespace
@@ -92,15 +102,23 @@ tc_status tc_dev_alloc(void **p, size_t bytes, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
     auto &fl = g_free[dev];
     auto it = fl.lower_bound(size);
-    if (it != fl.end() && it->first <= 2 * size) {
+    // a cached block up to twice the size is reused; under a limit only up
+    // to 1/16 more, so that held blocks track the sizes callers budget for
+    const size_t reuse_max = g_limit > 0 ? size + size / 16 : 2 * size;
+    if (it != fl.end() && it->first <= reuse_max) {
         void *ptr = it->second.first;
         Block b = it->second.second;
         fl.erase(it);
         if (b.stream != s && b.ev) TC_HIP(hipStreamWaitEvent(s, b.ev, 0));
         b.stream = s;
         g_used[ptr] = b;
+        note_in_use(dev, (int64_t)b.size);
         *p = ptr;
         return TC_OK;
+    }
+    if (g_limit > 0 && g_held[dev] + (int64_t)size > g_limit) {
+        release_cached(dev);  // cached blocks count against the limit: give them back first
+        if (g_held[dev] + (int64_t)size > g_limit) return TC_ERR_BUDGET;
     }
     void *ptr = nullptr;
     hipError_t e = hipMalloc(&ptr, size);
@@ -118,6 +136,9 @@ tc_status tc_dev_alloc(void **p, size_t bytes, hipStream_t s) {
     b.stream = s;
     b.device = dev;
     g_used[ptr] = b;
+    g_held[dev] += (int64_t)size;
+    if (g_held[dev] > g_peak_held[dev]) g_peak_held[dev] = g_held[dev];
+    note_in_use(dev, (int64_t)size);
     *p = ptr;
     return TC_OK;
 }
@@ -132,6 +153,7 @@ void tc_dev_free(void *p, hipStream_t s) {
     if (!b.ev && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) b.ev = nullptr;
     if (b.ev) (void)hipEventRecord(b.ev, s);
     b.stream = s;
+    note_in_use(b.device, -(int64_t)b.size);
     g_free[b.device].emplace(b.size, std::make_pair(p, b));
 }
 
@@ -318,7 +340,8 @@ tc_status tc_graph_from_edges(const int32_t *src, const int32_t *dst, int64_t nu
 }
 
 tc_status tc_graph_from_csr(const int64_t *row_ptr, const int32_t *col, int32_t n,
-                            int32_t mem_kind, void *stream, tc_graph **out) {
+                            int32_t mem_kind, int32_t assume_simple_sorted, void *stream,
+                            tc_graph **out) {
     if (!out) return TC_ERR_INVALID_ARG;
     *out = nullptr;
     if (n < 0 || !row_ptr || !valid_kind(mem_kind)) return TC_ERR_INVALID_ARG;
@@ -358,7 +381,7 @@ tc_status tc_graph_from_csr(const int64_t *row_ptr, const int32_t *col, int32_t 
         d_col = c;
     }
     int32_t *d_src = nullptr;
-    if (nnz > 0) {
+    if (nnz > 0 && !assume_simple_sorted) {
         TC_TRY(tmp.get(&d_src, nnz));
         k_csr_expand<<<grid_for(nnz), BK, 0, s>>>(d_rp, n, nnz, d_src);
         TC_LAUNCHED();
@@ -367,7 +390,10 @@ tc_status tc_graph_from_csr(const int64_t *row_ptr, const int32_t *col, int32_t 
     TC_TRY(new_graph(n, 1, &g));
     g->last_stream = s;
     tc_prof_mark(g, 0, s);
-    tc_status st = tc_build_from_pairs(g, d_src, d_col, nnz, nullptr, nullptr, 1, s);
+    tc_status st = assume_simple_sorted
+                       ? tc_build_from_pairs(g, nullptr, nullptr, 0, nullptr, nullptr, 1, s, d_rp,
+                                             d_col)
+                       : tc_build_from_pairs(g, d_src, d_col, nnz, nullptr, nullptr, 1, s);
     if (st >= 0) st = finish_build(g, s);
     if (st < 0) {
         tc_graph_destroy(g);
@@ -523,6 +549,11 @@ tc_status tc_get_results(const tc_graph *g, uint64_t *tri, uint64_t *support, ui
     return TC_OK;
 }
 
+tc_status tc_batch_get_results(const tc_graph *b, uint64_t *tri, uint64_t *support, uint64_t *triG,
+                               uint64_t *num, double *tc, int32_t mem_kind, void *stream) {
+    return tc_get_results(b, tri, support, triG, num, tc, mem_kind, stream);
+}
+
 tc_status tc_graph_device_bytes(const tc_graph *g, int64_t *bytes) {
     if (!g || !bytes) return TC_ERR_INVALID_ARG;
     *bytes = (int64_t)g->bytes;
@@ -601,6 +632,35 @@ tc_status tc_trim_memory(void) {
     }
     TC_HIP(hipSetDevice(cur));
     return TC_OK;
+}
+
+tc_status tc_set_memory_limit(int64_t bytes) {
+    if (bytes < 0) return TC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_limit = bytes;
+    return TC_OK;
+}
+
+tc_status tc_memory_stats(int64_t *held, int64_t *in_use, int64_t *peak_held, int64_t *peak_in_use,
+                          int32_t reset_peaks) {
+    int dev = 0;
+    TC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEV) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    if (held) *held = g_held[dev];
+    if (in_use) *in_use = g_in_use[dev];
+    if (peak_held) *peak_held = g_peak_held[dev];
+    if (peak_in_use) *peak_in_use = g_peak_in_use[dev];
+    if (reset_peaks) {
+        g_peak_held[dev] = g_held[dev];
+        g_peak_in_use[dev] = g_in_use[dev];
+    }
+    return TC_OK;
+}
+
+tc_status tc_compute_bytes(tc_graph *g, const tc_tuning *tuning, void *stream, int64_t *bytes) {
+    if (!g || !bytes) return TC_ERR_INVALID_ARG;
+    return tc_count_bytes(g, tuning, (hipStream_t)stream, bytes);
 }
 
 tc_status tc_set_profiling(int32_t on) {

@@ -172,6 +172,48 @@ __global__ __launch_bounds__(UQ_BLOCK) void k_unique_emit(const uint64_t *__rest
     }
 }
 
+// A CSR given as simple and sorted: each row strictly increasing, ids in
+// [0, n), no self-loop (checked: a violation sets err).  Its entries above
+// the diagonal, row by row, are the canonical edges in order; cnt[v] counts
+// row v's.
+__global__ void k_csr_upper_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                  int32_t n, uint32_t *__restrict__ cnt,
+                                  uint32_t *__restrict__ err) {
+    GRID_STRIDE(v, n) {
+        const int64_t a = rp[v], b = rp[v + 1];
+        bool bad = b < a;
+        uint32_t c = 0;
+        for (int64_t j = a; j < b && !bad; ++j) {
+            const int32_t x = col[j];
+            bad = x < 0 || x >= n || x == (int32_t)v || (j > a && col[j - 1] >= x);
+            c += x > (int32_t)v ? 1u : 0u;
+        }
+        if (bad) atomicOr(err, 1u);
+        cnt[v] = bad ? 0u : c;
+    }
+}
+
+// Writes row v's upper entries as canonical edges off[v] .. off[v] + cnt[v]
+// - 1 and their run [us[v], ue[v]) (left zero for an empty run).
+__global__ void k_csr_upper_emit(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                 int32_t n, const uint32_t *__restrict__ cnt,
+                                 const uint32_t *__restrict__ off, int32_t *__restrict__ eu,
+                                 int32_t *__restrict__ ev, uint32_t *__restrict__ us,
+                                 uint32_t *__restrict__ ue) {
+    GRID_STRIDE(v, n) {
+        const uint32_t c = cnt[v];
+        if (c == 0) continue;
+        const int64_t b = rp[v + 1], first = b - c;
+        const uint32_t o = off[v];
+        for (int64_t j = first; j < b; ++j) {
+            eu[o + (j - first)] = (int32_t)v;
+            ev[o + (j - first)] = col[j];
+        }
+        us[v] = o;
+        ue[v] = o + c;
+    }
+}
+
 __global__ void k_last_run(int64_t m, const int32_t *__restrict__ eu, uint32_t *__restrict__ ue) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ue[eu[m - 1]] = (uint32_t)m;
 }
@@ -822,7 +864,8 @@ tc_status tc_orient(tc_graph *g, hipStream_t s) {
 // ---------------------------------------------------------------------------
 tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t P,
                               const int64_t *d_vtx_off, const int64_t *d_pair_off,
-                              int32_t num_graphs, hipStream_t s) {
+                              int32_t num_graphs, hipStream_t s, const int64_t *simple_rp,
+                              const int32_t *simple_col) {
     const int32_t n = g->n;
     const int bits = g->bits;
     const uint64_t sentinel = (bits >= 32) ? ~0ull : ((1ull << (2 * bits)) - 1);
@@ -843,7 +886,32 @@ tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *
 
     // -- 1. canonical edges ---------------------------------------------------
     int64_t m = 0;
-    if (P > 0) {
+    if (simple_rp && n > 0) {
+        // a simple sorted CSR: the upper triangle, no sort and no dedup
+        uint32_t *cnt = nullptr, *off = nullptr, *d_m = nullptr;
+        TC_TRY(tmp.get(&cnt, nn));
+        TC_TRY(tmp.get(&off, nn));
+        TC_TRY(tmp.get(&d_m, 1));
+        k_csr_upper_count<<<grid_for(n), BK, 0, s>>>(simple_rp, simple_col, n, cnt, g->err);
+        TC_LAUNCHED();
+        TC_TRY(tc_scan_u32(cnt, off, n, d_m, s));
+        uint32_t h_m = 0, h_err = 0;
+        TC_HIP(hipMemcpyAsync(&h_err, g->err, 4, hipMemcpyDeviceToHost, s));
+        TC_HIP(hipMemcpyAsync(&h_m, d_m, 4, hipMemcpyDeviceToHost, s));
+        TC_HIP(hipStreamSynchronize(s));
+        if (h_err) return TC_ERR_INVALID_ARG;
+        m = h_m;
+        TC_TRY(tc_graph_alloc(g, &g->eu, m, s));
+        TC_TRY(tc_graph_alloc(g, &g->ev, m, s));
+        if (m > 0) {
+            k_csr_upper_emit<<<grid_for(n), BK, 0, s>>>(simple_rp, simple_col, n, cnt, off, g->eu,
+                                                        g->ev, us, ue);
+            TC_LAUNCHED();
+        }
+    } else if (simple_rp) {
+        TC_TRY(tc_graph_alloc(g, &g->eu, 0, s));
+        TC_TRY(tc_graph_alloc(g, &g->ev, 0, s));
+    } else if (P > 0) {
         uint64_t *keys = nullptr, *keys2 = nullptr;
         TC_TRY(tmp.get(&keys, P));
         TC_TRY(tmp.get(&keys2, P));

@@ -283,6 +283,44 @@ static bool tuning_valid(const tc_tuning *t) {
            t->light_bitmap_pairs >= 0;
 }
 
+// The pivot form AUTO (or the tuning) takes for this graph.
+static int choose_algo(const tc_graph *g, const tc_tuning &t) {
+    if (t.algorithm != TC_ALGO_AUTO) return t.algorithm;
+    const int64_t m = g->m;
+    const bool mid = m >= AUTO_MID_MIN_EDGES_FLAT ||
+                     (m >= AUTO_MID_MIN_EDGES && g->max_dplus >= AUTO_MID_MIN_DPLUS);
+    return mid ? TC_ALGO_MID_PIVOT : TC_ALGO_LOW_PIVOT;
+}
+
+tc_status tc_count_bytes(tc_graph *g, const tc_tuning *tin, hipStream_t s, int64_t *bytes) {
+    tc_tuning t;
+    if (tin) t = *tin; else tc_tuning_default(&t);
+    if (!tuning_valid(&t)) return TC_ERR_INVALID_ARG;
+    const int64_t m = g->m, nn = g->n > 0 ? g->n : 1, G = g->num_graphs;
+    // both forms: support per oriented slot and per edge, tri, num, tc, triG
+    int64_t b = 8 * m + 24 * nn + 8 * (G + 1);
+    if (m > 0 && g->max_dplus >= 2 && choose_algo(g, t) == TC_ALGO_MID_PIVOT) {
+        int64_t words = 0;
+        TC_TRY(tc_mid_bit_words(g, &words, s));
+        // transposition (pair lists and offsets), bit matrices with their
+        // row records and offsets, the 16-bit columns; temporaries of the
+        // transposition sort, work-item lists, support reordering and
+        // aggregation, all counted at once
+        b += 8 * m + 8 * (nn + 1) + 4 * words + 16 * nn + 8 * (nn + 1) + 2 * (m + 66) +
+             30 * m + 96 * nn;
+    } else {
+        // flags, symmetric adjacency with its slot map; temporaries of the
+        // bins and the aggregation
+        b += 2 * m + 16 * m + 16 * m + 40 * nn;
+    }
+    // the caching allocator rounds each block up: by under 512 bytes below
+    // 1 MiB, by under 2 MiB above; at most 64 blocks, each above 1 MiB
+    // taking at least 1 MiB of b
+    const int64_t big = (b >> 20) < 64 ? (b >> 20) : 64;
+    *bytes = b + 64 * 512 + big * ((int64_t)2 << 20);
+    return TC_OK;
+}
+
 tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
     tc_tuning t;
     if (tin) t = *tin; else tc_tuning_default(&t);
@@ -315,12 +353,7 @@ tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
     // first below about 0.6 M edges, and, on graphs whose oriented rows all
     // stay short (no degree skew, e.g. ER at average degree 16), up to a few
     // million.
-    int algo = t.algorithm;
-    if (algo == TC_ALGO_AUTO) {
-        const bool mid = m >= AUTO_MID_MIN_EDGES_FLAT ||
-                         (m >= AUTO_MID_MIN_EDGES && g->max_dplus >= AUTO_MID_MIN_DPLUS);
-        algo = mid ? TC_ALGO_MID_PIVOT : TC_ALGO_LOW_PIVOT;
-    }
+    const int algo = choose_algo(g, t);
     g->algo_used = algo;
     if (algo == TC_ALGO_MID_PIVOT) return tc_count_mid(g, t, lds_limit, max_entries, found, s);
     const int light_max = t.light_max_dplus;

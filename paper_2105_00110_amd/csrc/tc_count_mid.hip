@@ -1034,6 +1034,15 @@ __global__ void k_row_words(int32_t n, const int64_t *__restrict__ orp, int64_t 
     GRID_STRIDE(r, n) out[r] = bit_words(orp[r + 1] - orp[r]);
 }
 
+// Σ_r bit_words(|N_H(r)|): the words of every row's bit matrix.
+__global__ void k_row_words_total(int32_t n, const int64_t *__restrict__ orp,
+                                  unsigned long long *__restrict__ total) {
+    unsigned long long acc = 0;
+    GRID_STRIDE(r, n) acc += (unsigned long long)bit_words(orp[r + 1] - orp[r]);
+    acc = tc_wave_sum(acc);
+    if (__lane_id() == 0 && acc) atomicAdd(total, acc);
+}
+
 // Work per bin for the statistics: scan lengths of every pair, binned by
 // the pivot's |N_H|.
 __global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
@@ -1399,5 +1408,25 @@ tc_status tc_mid_stats(tc_graph *g, unsigned long long *acc, hipStream_t s) {
     const unsigned pg = grid_for(g->n) < 4096u ? grid_for(g->n) : 4096u;
     k_mid_pivots<<<pg, BK, 0, s>>>(g->n, g->orp, g->in_ptr, light_max, huge_min, acc);
     TC_LAUNCHED();
+    return TC_OK;
+}
+
+tc_status tc_mid_bit_words(const tc_graph *g, int64_t *words, hipStream_t s) {
+    if (g->rowbase) {
+        *words = g->bit_words;
+        return TC_OK;
+    }
+    tc_scratch tmp(s);
+    unsigned long long *d = nullptr;
+    TC_TRY(tmp.get(&d, 1));
+    TC_HIP(hipMemsetAsync(d, 0, 8, s));
+    if (g->n > 0) {
+        k_row_words_total<<<grid_for(g->n), BK, 0, s>>>(g->n, g->orp, d);
+        TC_LAUNCHED();
+    }
+    unsigned long long h = 0;
+    TC_HIP(hipMemcpyAsync(&h, d, 8, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    *words = (int64_t)h;
     return TC_OK;
 }

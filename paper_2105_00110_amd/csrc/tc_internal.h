@@ -41,11 +41,11 @@ static inline int tc_bits_for(uint64_t max_value) {
 }
 
 // ---------------------------------------------------------------------------
-// Device memory: stream-ordered allocation (hipMallocAsync / hipFreeAsync
-// on the device's default memory pool, whose release threshold is raised
-// so freed blocks stay cached for the next graph).  A block freed on one
-// stream is handed to another stream only after the freeing stream's
-// prior work, so temporaries never race with queued kernels.
+// Device memory: the library's caching allocator (tc_api.hip).  A block
+// freed on one stream is handed to another stream only after the freeing
+// stream's prior work, so temporaries never race with queued kernels.  With
+// a limit set (tc_set_memory_limit), an allocation that would push the
+// device bytes the library holds past it fails with TC_ERR_BUDGET.
 // ---------------------------------------------------------------------------
 tc_status tc_dev_alloc(void **p, size_t bytes, hipStream_t s);
 void tc_dev_free(void *p, hipStream_t s);
@@ -196,9 +196,14 @@ bool tc_profiling_on();
 void tc_prof_mark(tc_graph *g, int idx, hipStream_t s);
 
 // Pipeline stages (tc_build.hip, tc_count.hip, tc_aggregate.hip).
+// Canonical edges from pairs (sorted and deduplicated), or, with simple_rp
+// given, from a simple sorted CSR (simple_rp / simple_col, device): the
+// entries above the diagonal, taken in order.
 tc_status tc_build_from_pairs(tc_graph *g, const int32_t *d_src, const int32_t *d_dst,
                               int64_t P, const int64_t *d_pair_vtx_base,
-                              const int64_t *d_pair_off, int32_t num_graphs, hipStream_t s);
+                              const int64_t *d_pair_off, int32_t num_graphs, hipStream_t s,
+                              const int64_t *simple_rp = nullptr,
+                              const int32_t *simple_col = nullptr);
 tc_status tc_orient(tc_graph *g, hipStream_t s);
 tc_status tc_count(tc_graph *g, const tc_tuning *t, hipStream_t s);
 tc_status tc_aggregate(tc_graph *g, hipStream_t s);
@@ -213,6 +218,12 @@ tc_status tc_mid_prepare(tc_graph *g, hipStream_t s);
 tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_entries,
                        unsigned long long *found, hipStream_t s);
 tc_status tc_mid_stats(tc_graph *g, unsigned long long *acc, hipStream_t s);
+// Words of the middle pivot's bit matrices, Σ_r Σ_{t<|N_H(r)|} ceil(t/32)
+// (device reduction and one read-back; the stored total once they exist).
+tc_status tc_mid_bit_words(const tc_graph *g, int64_t *words, hipStream_t s);
+// Upper bound of the device bytes tc_count + tc_aggregate allocate beyond
+// what g holds, for the pivot form the tuning (or AUTO) picks.
+tc_status tc_count_bytes(tc_graph *g, const tc_tuning *tuning, hipStream_t s, int64_t *bytes);
 
 template <typename T>
 tc_status tc_graph_alloc(tc_graph *g, T **p, int64_t count, hipStream_t s) {

@@ -73,7 +73,7 @@ _SIGS = {
     "tc_status_string": (ctypes.c_char_p, [_i32]),
     "tc_tuning_default": (_st, [ctypes.POINTER(tc_tuning)]),
     "tc_graph_from_edges": (_st, [_vp, _vp, _i64, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
-    "tc_graph_from_csr": (_st, [_vp, _vp, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
+    "tc_graph_from_csr": (_st, [_vp, _vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
     "tc_batch_create": (_st, [_vp, _vp, _vp, _vp, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
     "tc_fused_tuning_default": (_st, [ctypes.POINTER(tc_fused_tuning)]),
     "tc_batch_fused_workspace_bytes": (_i64, [_i64, _i64, _i32]),
@@ -90,6 +90,7 @@ _SIGS = {
     "tc_num_edges": (_i64, [_vp]),
     "tc_get_edges": (_st, [_vp, _vp, _vp, _i32, _vp]),
     "tc_get_results": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "tc_batch_get_results": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "tc_numerator_algebraic": (_st, [_vp, _vp, _i32, _vp]),
     "tc_trim_memory": (_st, []),
     "tc_edge_text_read": (_st, [ctypes.c_char_p, _vp, _vp, _i64, ctypes.POINTER(_i64),
@@ -97,6 +98,9 @@ _SIGS = {
     "tc_relabel_ids": (_st, [_vp, _vp, _i64, _vp, _vp, _vp, ctypes.POINTER(_i64), _i32, _vp]),
     "tc_graph_device_bytes": (_st, [_vp, ctypes.POINTER(_i64)]),
     "tc_estimate_device_bytes": (_i64, [_i64, _i32]),
+    "tc_compute_bytes": (_st, [_vp, ctypes.POINTER(tc_tuning), _vp, ctypes.POINTER(_i64)]),
+    "tc_set_memory_limit": (_st, [_i64]),
+    "tc_memory_stats": (_st, [ctypes.POINTER(_i64)] * 4 + [_i32]),
     "tc_graph_destroy": (None, [_vp]),
     "tc_top_k": (_st, [_vp, _i32, _vp, _vp, ctypes.POINTER(_i32), _i32, _vp]),
     "tc_set_profiling": (_st, [_i32]),
@@ -157,9 +161,10 @@ def tc_graph_from_edges(src, dst, num_pairs, n, mem_kind, stream):
     return h
 
 
-def tc_graph_from_csr(row_ptr, col, n, mem_kind, stream):
+def tc_graph_from_csr(row_ptr, col, n, mem_kind, assume_simple_sorted, stream):
     h = _vp()
-    _check(load().tc_graph_from_csr(row_ptr, col, int(n), int(mem_kind), stream, ctypes.byref(h)),
+    _check(load().tc_graph_from_csr(row_ptr, col, int(n), int(mem_kind),
+                                    1 if assume_simple_sorted else 0, stream, ctypes.byref(h)),
            "tc_graph_from_csr")
     return h
 
@@ -239,6 +244,11 @@ def tc_get_results(h, tri, support, triG, num, tc, mem_kind, stream):
                   "tc_get_results")
 
 
+def tc_batch_get_results(h, tri, support, triG, num, tc, mem_kind, stream):
+    return _check(load().tc_batch_get_results(h, tri, support, triG, num, tc, int(mem_kind),
+                                              stream), "tc_batch_get_results")
+
+
 def tc_numerator_algebraic(h, num, mem_kind, stream):
     return _check(load().tc_numerator_algebraic(h, num, int(mem_kind), stream),
                   "tc_numerator_algebraic")
@@ -298,6 +308,27 @@ def tc_graph_device_bytes(h):
 
 def tc_estimate_device_bytes(num_pairs, n):
     return int(load().tc_estimate_device_bytes(int(num_pairs), int(n)))
+
+
+def tc_compute_bytes(h, tuning=None, stream=None):
+    b = _i64(0)
+    t = None
+    if tuning is not None:
+        t = tuning if isinstance(tuning, tc_tuning) else tuning_from_dict(tuning)
+        t = ctypes.byref(t)
+    _check(load().tc_compute_bytes(h, t, stream, ctypes.byref(b)), "tc_compute_bytes")
+    return int(b.value)
+
+
+def tc_set_memory_limit(nbytes):
+    return _check(load().tc_set_memory_limit(int(nbytes)), "tc_set_memory_limit")
+
+
+def tc_memory_stats(reset_peaks=False):
+    v = [_i64(0) for _ in range(4)]
+    _check(load().tc_memory_stats(*[ctypes.byref(x) for x in v], 1 if reset_peaks else 0),
+           "tc_memory_stats")
+    return dict(zip(("held", "in_use", "peak_held", "peak_in_use"), (int(x.value) for x in v)))
 
 
 def tc_graph_destroy(h):
@@ -379,7 +410,7 @@ class Graph:
         return cls(h, stream)
 
     @classmethod
-    def from_csr(cls, row_ptr, col, n, stream=None):
+    def from_csr(cls, row_ptr, col, n, stream=None, assume_simple_sorted=False):
         dev = _is_torch(row_ptr) and row_ptr.is_cuda
         if dev:
             if stream is None:
@@ -388,7 +419,7 @@ class Graph:
             row_ptr = np.ascontiguousarray(row_ptr, np.int64)
             col = np.ascontiguousarray(col, np.int32)
         h = tc_graph_from_csr(_ptr(row_ptr), _ptr(col), n, TC_MEM_DEVICE if dev else TC_MEM_HOST,
-                              stream)
+                              assume_simple_sorted, stream)
         return cls(h, stream)
 
     @classmethod
@@ -429,6 +460,11 @@ class Graph:
 
     def device_bytes(self):
         return tc_graph_device_bytes(self.h)
+
+    def compute_bytes(self, tuning=None):
+        """Upper bound of the device bytes compute(tuning) adds (waits for
+        the handle's stream)."""
+        return tc_compute_bytes(self.h, tuning, self.stream)
 
     def compute(self, tuning=None):
         if tuning is None:

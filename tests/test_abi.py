@@ -44,6 +44,10 @@ def test_host_only_calls():
     assert lib.tc_graph_from_edges(None, None, -1, 5, 0, None, ctypes.byref(h)) == tc.TC_ERR_INVALID_ARG
     assert lib.tc_graph_from_edges(None, None, 0, 5, 7, None, ctypes.byref(h)) == tc.TC_ERR_INVALID_ARG
     assert lib.tc_numerator_algebraic(None, None, 0, None) == tc.TC_ERR_INVALID_ARG
+    b = ctypes.c_int64(0)
+    assert lib.tc_compute_bytes(None, None, None, ctypes.byref(b)) == tc.TC_ERR_INVALID_ARG
+    assert lib.tc_set_memory_limit(-1) == tc.TC_ERR_INVALID_ARG
+    assert lib.tc_set_memory_limit(0) == tc.TC_OK
 
 
 def test_fused_argument_checks_on_host():

@@ -246,6 +246,64 @@ def test_from_csr_matches_edges(tclib):
     assert_parity(res, ref)
 
 
+def _csr(rows, cols, n):
+    order = np.lexsort((cols, rows))
+    r, c = rows[order], cols[order]
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, r + 1, 1)
+    return np.cumsum(rp), np.ascontiguousarray(c, np.int32)
+
+
+@pytest.mark.parametrize("scale", [12, 16])
+def test_from_simple_sorted_csr(tclib, scale):
+    # the fast path of tc_graph_from_csr for a CSR stated to be simple and
+    # sorted: the symmetric CSR of the oracle's canonical edges, and its
+    # upper triangle alone, give the oracle's results; on the host and on
+    # the device
+    src, dst, n = gg.rmat(scale, 16, seed=6)
+    ref = native.o2_paper(src, dst, n)
+    sym = _csr(np.concatenate([ref.eu, ref.ev]), np.concatenate([ref.ev, ref.eu]), n)
+    upper = _csr(ref.eu, ref.ev, n)
+    for name, (rp, col) in (("symmetric", sym), ("upper", upper)):
+        for dev in (False, True):
+            _say("simple sorted CSR", name, "device" if dev else "host", "scale", scale)
+            if dev:
+                g = tclib.Graph.from_csr(torch.as_tensor(rp).cuda(), torch.as_tensor(col).cuda(), n,
+                                         assume_simple_sorted=True)
+            else:
+                g = tclib.Graph.from_csr(rp, col, n, assume_simple_sorted=True)
+            st = g.compute()
+            res = g.results()
+            res["eu"], res["ev"] = g.edges()
+            res["status"], res["m"] = st, g.m
+            g.close()
+            assert_parity(res, ref)
+
+
+def test_simple_sorted_csr_violations_are_refused(tclib):
+    # rows not increasing, a self-loop, a duplicate, an id out of range:
+    # with the simple-sorted statement each is refused, without it each is
+    # normalised like any pair list
+    n = 6
+    good_rows = np.array([0, 0, 1, 2, 3], np.int32)
+    good_cols = np.array([1, 2, 2, 3, 4], np.int32)
+    rp5 = np.array([0, 2, 3, 4, 5, 5, 5], np.int64)  # rows of 2, 1, 1, 1 entries, then empty
+    bad = {
+        "unsorted": (rp5, np.array([2, 1, 2, 3, 4], np.int32)),
+        "loop": (rp5, np.array([1, 2, 1, 3, 4], np.int32)),
+        "duplicate": (rp5, np.array([1, 1, 2, 3, 4], np.int32)),
+        "range": (rp5, np.array([1, 2, 2, 3, 9], np.int32)),
+    }
+    rp, col = _csr(good_rows, good_cols, n)
+    g = tclib.Graph.from_csr(rp, col, n, assume_simple_sorted=True)
+    g.close()
+    for name, (rp, col) in bad.items():
+        _say("simple sorted CSR violation", name)
+        with pytest.raises(tclib.TCError) as ei:
+            tclib.Graph.from_csr(rp, col, n, assume_simple_sorted=True)
+        assert ei.value.status == tclib.TC_ERR_INVALID_ARG
+
+
 def test_degenerate_inputs(tclib):
     e = np.zeros(0, np.int32)
     _say("empty n=0")

@@ -8,6 +8,9 @@
   to 2e7 edges;
   graphs kept resident answer later top-k and vertex queries, also under a
   budget tight enough to evict them.
+* Memory: tc_compute_bytes bounds what the count allocates; a dense request
+  whose bit matrices outgrow the estimate from its pair count is refused
+  under a budget below its exact need and served inside one above it.
 * Autotuner: a short search leaves every result unchanged.
 """
 import numpy as np
@@ -172,6 +175,98 @@ def test_serving_budget_rejects_and_bounds(tclib):
     assert srv.stats["rejected"] == sum(e > budget for e in est)
 
 
+def _clique(k):
+    iu = np.triu_indices(k, 1)
+    return iu[0].astype(np.int32), iu[1].astype(np.int32), k
+
+
+def _check_clique(res, k):
+    # K_k: every vertex on C(k-1, 2) triangles, every edge on k-2, every
+    # neighbour's weight 1, so num(v) = k·C(k-1, 2) = 3·△(G) and tc = 1
+    c2 = (k - 1) * (k - 2) // 2
+    assert np.all(res["tri"] == c2) and np.all(res["support"] == k - 2)
+    assert int(res["triG"][0]) == k * (k - 1) * (k - 2) // 6
+    assert np.all(res["num"] == k * c2) and np.all(res["tc"] == 1.0)
+
+
+@pytest.mark.parametrize("case", ["clique3000", "rmat16", "er_low_pivot", "batch"])
+def test_compute_bytes_bounds_what_the_count_allocates(tclib, case):
+    # with the cache emptied after the build, every block the count takes is
+    # new: the growth of the allocator's held bytes is what it allocates
+    if case == "clique3000":
+        src, dst, n = _clique(3000)
+        g = tclib.Graph.from_edges(src, dst, n)
+    elif case == "rmat16":
+        src, dst, n = gg.rmat(16, 16, seed=16)
+        g = tclib.Graph.from_edges(src, dst, n)
+    elif case == "er_low_pivot":
+        src, dst, n = gg.er(20000, 1e-3, seed=3)
+        g = tclib.Graph.from_edges(src, dst, n)
+    else:
+        src, dst, po, vo = gg.batched_ba(64, seed=64)
+        g = tclib.Graph.batch(src, dst, po, vo)
+    tclib.tc_trim_memory()
+    need = g.compute_bytes()
+    s0 = tclib.tc_memory_stats(reset_peaks=True)
+    g.compute()
+    torch.cuda.synchronize()
+    s1 = tclib.tc_memory_stats()
+    grown = s1["peak_held"] - s0["held"]
+    _say(case, "pairs", len(src), "algorithm", g.work_stats()["algorithm"], "bound", need,
+         "held growth", grown, "ratio", round(grown / need, 3))
+    if case == "clique3000":
+        _check_clique(g.results(), 3000)
+    g.close()
+    assert 0 < grown <= need
+
+
+def test_dense_request_stays_inside_a_tight_budget(tclib):
+    # K_3000: the bit matrices of the middle pivot (about Σ C(d+, 2) / 8
+    # bytes) outgrow the estimate from the pair count; the second admission
+    # step sees the exact need after the orientation
+    import dataclasses
+
+    from paper_2105_00110_amd import serve
+    k = 3000
+    src, dst, n = _clique(k)
+    dense = serve.Request(0, src, dst, n, family="clique")
+    est = serve.estimate_bytes([dense])
+    g = tclib.Graph.from_edges(src, dst, n)
+    need = g.device_bytes() + g.compute_bytes()
+    g.close()
+    _say("clique", k, "estimate", est, "exact need", need)
+    assert need > est
+    # a budget between the estimate and the need: the budget error, no overrun
+    budget = (est + need) // 2
+    tclib.tc_trim_memory()
+    tclib.tc_memory_stats(reset_peaks=True)
+    srv = serve.Server(serve.ServerConfig(budget_bytes=budget, streams=2))
+    rep = srv.run([dense])
+    _say("budget", budget, srv.stats, tclib.tc_memory_stats())
+    assert rep[0].error is not None and "budget" in rep[0].error
+    assert tclib.tc_memory_stats()["peak_held"] <= budget
+    srv.close()
+    # a budget a little above the need, with small requests arriving beside
+    small = serve.make_requests(10, seed=51, m_lo=1e3, m_hi=2e5, workers=4)
+    reqs = [dataclasses.replace(dense, need=0, solo=False, retries=0)] + \
+        [dataclasses.replace(r, rid=i + 1) for i, r in enumerate(small)]
+    budget = need + (256 << 20)
+    tclib.tc_trim_memory()
+    tclib.tc_memory_stats(reset_peaks=True)
+    srv = serve.Server(serve.ServerConfig(budget_bytes=budget, streams=4))
+    replies = srv.run(reqs)
+    stats = tclib.tc_memory_stats()
+    _say("budget", budget, srv.stats, stats)
+    assert all(r.error is None for r in replies)
+    assert stats["peak_held"] <= budget and srv.stats["peak_bytes"] <= budget
+    assert srv.stats["grown"] + srv.stats["requeued"] >= 1
+    srv.close()
+    _check_clique(replies[0].results, k)
+    for r in replies[1:]:
+        q = reqs[r.rid]
+        _check_oracle(r.results, native.o2_paper(q.src, q.dst, q.n))
+
+
 def test_autotune_keeps_results(tclib, tmp_path):
     from paper_2105_00110_amd import autotune
     src, dst, n = gg.rmat(14, 16, seed=14)
@@ -208,7 +303,9 @@ def test_serving_resident_graphs_answer_later_queries(tclib):
         else:
             q = ("vertices", rng.integers(0, base[i].n, 7))
         reqs.append(dataclasses.replace(base[i], rid=len(reqs), key=("g", i), query=q))
-    for budget in (8 << 30, 2 * max(serve.estimate_bytes([r]) for r in base)):
+    # the tight budget: twice the largest keyed request (keyed requests keep a
+    # handle, so their estimate is the handle path's)
+    for budget in (8 << 30, 2 * max(serve.estimate_bytes([r]) for r in reqs[:len(base)])):
         srv = serve.Server(serve.ServerConfig(budget_bytes=budget, streams=3))
         replies = srv.run(reqs, serve.poisson_arrivals(len(reqs), 2000.0, seed=31))
         _say("resident serving, budget", budget, srv.stats)

@@ -1,6 +1,7 @@
 """Host logic of the serving loop and the autotuner (no GPU)."""
 import collections
 import math
+import threading
 
 import numpy as np
 import pytest
@@ -50,6 +51,7 @@ class _R:
         self.dst = np.zeros(pairs, np.int32)
         self.arrival = 0.0
         self.key, self.query = key, query
+        self.need, self.solo, self.retries = 0, False, 0
 
     @property
     def pairs(self):
@@ -58,12 +60,16 @@ class _R:
 
 def _server(monkeypatch, **cfg):
     # a server without streams: only the unit former is exercised
-    monkeypatch.setattr(serve, "estimate_bytes", lambda reqs: 100 * sum(r.pairs for r in reqs))
+    monkeypatch.setattr(serve, "estimate_bytes",
+                        lambda reqs, kind="batch": 100 * sum(r.pairs for r in reqs))
+    cfg.setdefault("fused_pairs", 1)  # no tiny requests unless a test asks for them
     s = serve.Server.__new__(serve.Server)
     s.cfg = serve.ServerConfig(**cfg)
-    s.stats = {"evictions": 0}
+    s.stats = {"evictions": 0, "grown": 0, "requeued": 0, "rejected": 0, "peak_bytes": 0}
     s.resident = collections.OrderedDict()
     s.resident_bytes = 0
+    s._mu = threading.Lock()
+    s._used = 0
     return s
 
 
@@ -113,6 +119,22 @@ def test_form_unit_batches_small_in_order(monkeypatch):
     assert u.bytes == 100 * 239
 
 
+def test_form_unit_tiny_and_small_do_not_mix(monkeypatch):
+    # tiny requests (below fused_pairs) form a fused unit, small ones a
+    # batched handle; a unit holds consecutive requests of one class
+    s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250,
+                fused_pairs=30)
+    q = [_R(0, 10), _R(1, 29), _R(2, 60), _R(3, 5)]
+    u = s._form_unit(q, 10**9)
+    assert [r.rid for r in u.reqs] == [0, 1] and u.kind == "fused"
+    u = s._form_unit(q[2:], 10**9)
+    assert [r.rid for r in u.reqs] == [2] and u.kind == "batch"
+    # a tiny request over too many vertices for the fused launch is not tiny
+    big_n = _R(4, 10, n=serve.FUSED_MAX_N + 1)
+    u = s._form_unit([big_n, _R(5, 10)], 10**9)
+    assert [r.rid for r in u.reqs] == [4] and u.kind == "batch"
+
+
 def test_form_unit_large_alone(monkeypatch):
     s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250)
     q = [_R(0, 500), _R(1, 10)]
@@ -126,6 +148,54 @@ def test_form_unit_waits_and_rejects(monkeypatch):
     assert s._form_unit([_R(0, 101)], 10000) is serve._REJECT  # larger than the whole budget
     u = s._form_unit([_R(0, 40), _R(1, 50)], 5000)          # the second would exceed free memory
     assert [r.rid for r in u.reqs] == [0]
+
+
+def test_second_admission_grows_reservation_only_into_free_memory(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10000, small_pairs=100, batch_pairs=250)
+    u = serve._Unit([_R(0, 20)], 2000)
+    s._used = 6000  # this unit's 2000 included
+    s.resident_bytes = 1000
+    assert s._admit(u, 1500) and u.bytes == 2000 and s._used == 6000  # below: kept
+    assert s._admit(u, 5000) and u.bytes == 5000 and s._used == 9000  # 3000 free: grown
+    assert not s._admit(u, 6001) and u.bytes == 5000 and s._used == 9000  # 1000 free only
+    assert s.stats["grown"] == 1 and s.stats["peak_bytes"] == 10000
+
+
+def test_requeue_with_exact_need(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10000, small_pairs=100, batch_pairs=250)
+    q = [_R(7, 10), _R(8, 10)]
+    r = _R(3, 20)
+    assert s._requeue(serve._Unit([r], 2000), serve.Requeue(6000), q)
+    assert [x.rid for x in q] == [3, 7, 8] and r.need == 6000
+    # the next unit formed reserves the exact need, alone
+    assert s._form_unit(q, 5999) is None
+    u = s._form_unit(q, 6000)
+    assert [x.rid for x in u.reqs] == [3] and u.bytes == 6000
+    # a need above the whole budget is answered with the budget error
+    r2 = _R(4, 20)
+    assert not s._requeue(serve._Unit([r2], 2000), serve.Requeue(10001), [])
+    r2.need = 10001
+    assert s._form_unit([r2], 10000) is serve._REJECT
+
+
+def test_requeue_of_a_batch_runs_each_alone(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250)
+    reqs = [_R(0, 10), _R(1, 10), _R(2, 10)]
+    q = [_R(3, 10)]
+    assert s._requeue(serve._Unit(reqs, 3000), serve.Requeue(9000), q)
+    assert [x.rid for x in q] == [0, 1, 2, 3] and all(r.solo and r.need == 0 for r in reqs)
+    assert [x.rid for x in s._form_unit(q, 10**9).reqs] == [0]
+
+
+def test_requeue_after_library_limit_is_bounded(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250,
+                max_retries=2)
+    r = _R(0, 500)
+    for _ in range(2):
+        q = []
+        assert s._requeue(serve._Unit([r], 100), serve.Requeue(0), q) and q == [r]
+    assert not s._requeue(serve._Unit([r], 100), serve.Requeue(0), [])
+    assert r.retries == 3
 
 
 def test_latency_summary_skips_warmup():
