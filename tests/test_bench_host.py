@@ -32,11 +32,11 @@ def test_counter_summary_rule_and_shapes(tmp_path):
     d = tmp_path / "pmc"
     # dispatches: k_mid_block light shape (grid 100) first, heavy (grid 200)
     # second, in two steps; then the 1 GiB copy (three dispatches)
-    disp = [(MID, 100, 1), (MID, 200, 2), (MID, 100, 3), (MID, 200, 4),
+    disp = [(COPY, 4096, 0), (MID, 100, 1), (MID, 200, 2), (MID, 100, 3), (MID, 200, 4),
             (COPY, 4096, 5), (COPY, 4096, 6), (COPY, 4096, 7)]
     p1, p2 = [], []
     for name, grid, i in disp:
-        copy = name == COPY
+        copy = name == COPY and i > 0  # dispatch 0: a small copy of the same shape
         c1 = {"TCC_EA0_RDREQ_sum": 8388608 if copy else 1000 + grid,
               "TCC_EA0_RDREQ_32B_sum": 0 if copy else 10,
               "TCC_EA0_RDREQ_64B_sum": 0 if copy else 20,
