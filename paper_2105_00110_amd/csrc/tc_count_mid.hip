@@ -164,11 +164,13 @@ __global__ void k_item_write(int32_t n, const uint32_t *__restrict__ cnt,
 //              number of row entries before them; a probe is one 8-byte
 //              read, a bit test and a popcount.
 //   LK_BITMAP16  for pivots v among the top 2^16 ranks, whose candidates
-//              are 16-bit entries: the bitmap starts at rank v + 1 and has
-//              2048 words, which hold every rank a candidate can have, and
-//              any 16-bit value indexes inside it.  Words past the row's
-//              last entry read as no bits, so a probe needs no range test;
-//              a miss adds 0 to the lane's spare counter.
+//              are 16-bit entries (rank less rank16_base): the bitmap has
+//              2048 words indexed by the 16-bit value itself, so every
+//              value indexes inside it with no subtraction and no range
+//              test, and the bit-field reads take their offset and width
+//              from the value's low 5 bits.  Values at or below v's own
+//              hold no bits.  A probe reads the packed pairs of entries as
+//              loaded; a miss adds 0 to the lane's spare counter.
 // ---------------------------------------------------------------------------
 constexpr int LK_HASH = 0, LK_GLOBAL = 1, LK_BITMAP = 2, LK_BITMAP16 = 3;
 constexpr int BITMAP16_WORDS = 2048;
@@ -219,32 +221,6 @@ __device__ __forceinline__ void bitmap_probe_n(const BitmapRow &b, const uint32_
         hit[e] = ((w[e].x >> sh) & 1u) & in;
         const int pos = (int)(w[e].y + (uint32_t)__popc(w[e].x & ((1u << sh) - 1u)));
         q[e] = in ? pos : spare;
-    }
-}
-
-// The LK_BITMAP16 probe of the entries k0 .. k0 + N - 1 of a lane's run, of
-// which the first cnt - k0 lie in the tail: hit = 1 if the entry is in the
-// tail and in the row, q = the key's place in the row for a hit, else
-// spare.  Keys are 16-bit ranks on b.lo's footing; the index wraps within
-// 2^16, and the bit-field reads take their offset and width from the low 5
-// bits of d.
-template <int N>
-__device__ __forceinline__ void bitmap16_probe_n(const BitmapRow &b, const uint32_t (&key)[N],
-                                                 int k0, int cnt, int spare, int (&q)[N],
-                                                 uint32_t (&hit)[N]) {
-    uint32_t dd[N];
-    uint2 w[N];
-#pragma unroll
-    for (int e = 0; e < N; ++e) {
-        dd[e] = key[e] - b.lo;
-        w[e] = b.bm[__builtin_amdgcn_ubfe(dd[e], 5u, 11u)];
-    }
-#pragma unroll
-    for (int e = 0; e < N; ++e) {
-        const bool h = __builtin_amdgcn_ubfe(w[e].x, dd[e], 1u) != 0u && k0 + e < cnt;
-        const uint32_t pos = w[e].y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w[e].x, 0u, dd[e]));
-        hit[e] = h ? 1u : 0u;
-        q[e] = h ? (int)pos : spare;
     }
 }
 
@@ -341,6 +317,51 @@ __device__ __forceinline__ void mid_group(const int32_t *__restrict__ ocol,
             const int64_t kw = x - gx[p];
             const int64_t c0 = gs[p] + 32 * kw;
             const int cnt = min(32, gt[p] - 32 * (int)kw);
+            if constexpr (LK == LK_BITMAP16) {
+                // 17 aligned words hold the 32 entries from c0 (an odd c0
+                // starts in the upper half of the first); each aligned pair
+                // is probed as loaded: the lower entry is the word's low 16
+                // bits, whose low 5 bits the bit-field reads take as they
+                // are, the upper entry its high 16 bits
+                const uint32_t *o32 = reinterpret_cast<const uint32_t *>(ocol16);
+                const int64_t q = c0 >> 1;
+                const uint32_t sh = (uint32_t)(c0 & 1) << 4;
+                uint32_t dw[17];
+#pragma unroll
+                for (int j = 0; j < 17; ++j) dw[j] = o32[q + j];
+                uint32_t pk[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) pk[j] = __builtin_amdgcn_alignbit(dw[j + 1], dw[j], sh);
+                const int spare = dv + lane;
+                uint32_t mask = 0;
+#pragma unroll
+                for (int c = 0; c < 16; c += 4) {
+                    uint32_t key[8];
+                    uint2 w[8];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        key[2 * e] = pk[c + e];
+                        key[2 * e + 1] = pk[c + e] >> 16;
+                    }
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) w[e] = bmr.bm[__builtin_amdgcn_ubfe(key[e], 5u, 11u)];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int k = 2 * c + e;  // the entry's place in the run
+                        const uint32_t bit = __builtin_amdgcn_ubfe(w[e].x, key[e], 1u);
+                        const uint32_t at =
+                            w[e].y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w[e].x, 0u, key[e]));
+                        // an entry past the tail adds its bit to the spare
+                        // counter, which is never read
+                        atomicAdd(&lsup[bit != 0u && k < cnt ? (int)at : spare], bit);
+                        mask |= bit << k;
+                    }
+                }
+                if (cnt < 32) mask &= (1u << cnt) - 1u;
+                bits[gb[p] + kw] = mask;
+                found += (unsigned long long)__popc(mask);
+                continue;
+            }
             // whole 32-entry run (the arrays are padded past their end);
             // entries past the tail are masked to EMPTY
             uint32_t ww[32];
@@ -356,15 +377,8 @@ __device__ __forceinline__ void mid_group(const int32_t *__restrict__ ocol,
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const uint32_t a = __builtin_amdgcn_alignbit(dw[j + 1], dw[j], sh);
-                    if constexpr (LK == LK_BITMAP16) {
-                        // every value probes inside the bitmap: the hits of
-                        // entries past the tail are masked after the probe
-                        ww[2 * j] = a & 0xFFFFu;
-                        ww[2 * j + 1] = a >> 16;
-                    } else {
-                        ww[2 * j] = 2 * j < cnt ? (a & 0xFFFFu) : EMPTY;
-                        ww[2 * j + 1] = 2 * j + 1 < cnt ? (a >> 16) : EMPTY;
-                    }
+                    ww[2 * j] = 2 * j < cnt ? (a & 0xFFFFu) : EMPTY;
+                    ww[2 * j + 1] = 2 * j + 1 < cnt ? (a >> 16) : EMPTY;
                 }
             } else {
 #pragma unroll
@@ -386,18 +400,6 @@ __device__ __forceinline__ void mid_group(const int32_t *__restrict__ ocol,
 #pragma unroll
                     for (int e = 0; e < 8; ++e)
                         qc[e] = kk[e] <= hmax ? row_search(ocol, vstart, dv, kk[e]) : -1;
-                } else if constexpr (LK == LK_BITMAP16) {
-                    // entries past the tail keep no hit; a miss adds 0 to
-                    // this lane's spare counter, so lanes never share a
-                    // counter on misses
-                    uint32_t hb[8];
-                    bitmap16_probe_n<8>(bmr, kk, c, cnt, dv + lane, qc, hb);
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        mask |= hb[e] << (c + e);
-                        atomicAdd(&lsup[qc[e]], hb[e]);
-                    }
-                    continue;
                 } else if constexpr (LK == LK_BITMAP) {
                     // the counter index is always valid (the key's place in
                     // the row, or this lane's spare counter outside the
@@ -644,10 +646,11 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
         } else if constexpr (LK == LK_BITMAP) {
             for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
             if (n16 && wide16 && bitmap_words >= BITMAP16_WORDS) {
-                // LK_BITMAP16: 2048 words from rank v + 1
+                // LK_BITMAP16: 2048 words over the 16-bit values, that is
+                // ranks rel .. rel + 2^16 - 1
                 bmr.span = 32u * BITMAP16_WORDS;
-                bitmap_build(bm, scan, ocol, vstart, d, (uint32_t)v + 1u, bmr.span);
-                bmr.lo = (uint32_t)v + 1u - rel;
+                bitmap_build(bm, scan, ocol, vstart, d, rel, bmr.span);
+                bmr.lo = 0;
             } else {
                 const uint32_t lo = (uint32_t)ocol[vstart];
                 bmr.span = (uint32_t)ocol[vstart + d - 1] - lo + 1;
