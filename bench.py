@@ -841,22 +841,50 @@ def main():
     log("stage ms", json.dumps({k: round(v, 3) for k, v in stages.items()}))
     log("work", json.dumps(work))
 
-    # Roofline of the dominant kernel: algorithmic bytes per launch = the
-    # streamed candidates (4 B each, 2 B for those read as 16-bit entries:
-    # pivots among the top 2^16 ranks) + 8 B per scanned pair (its in-pair
-    # word) + 8 B per pivot row (row offsets).
-    bins = {"count_light": "light", "count_heavy": "heavy", "count_huge": "huge"}
-    dom = max(bins, key=lambda k: stages[k])
-    b = bins[dom]
-    c16 = work.get(f"cand_{b}_16", 0)
-    algo_bytes = (4 * (work[f"cand_{b}"] - c16) + 2 * c16 + 8 * work[f"edges_{b}"]
-                  + 8 * work[f"rows_{b}"])
-    dur_s = stages[dom] / 1e3
+    # Roofline of the dominant kernel, the count launch with the longest
+    # device time (each count launch is timed on its own stream by HIP
+    # events).  Algorithmic bytes per launch = the streamed candidates (4 B
+    # each, 2 B for those read as 16-bit entries: pivots among the top 2^16
+    # ranks) + 8 B per scanned pair (its in-pair word) + 8 B per pivot row.
+    # The workgroup pivots among the top 2^16 ranks have a launch of their
+    # own; the wavefront launches share the light bin's work statistics, so
+    # when one of them dominates the light stage is priced as a whole.
+    heavy16 = stages.get("count_heavy_bitmap16", 0.0)
+    launches = {
+        "count_heavy_bitmap16": heavy16,
+        "count_heavy": stages["count_heavy"] - heavy16,
+        "count_huge": stages["count_huge"],
+        "count_light": max(stages.get("count_light_groups", 0.0), stages.get("count_light_wave", 0.0),
+                           stages.get("count_light_bitmap", 0.0), 0.0)
+        if work.get("algorithm") == 2 else stages["count_light"],
+    }
+    dom = max(launches, key=lambda k: launches[k])
+    if dom == "count_heavy_bitmap16":
+        c16 = work["cand_heavy_16"]
+        algo_bytes = 2 * c16 + 8 * work["edges_heavy_16"] + 8 * work["rows_heavy_16"]
+        dur_ms = heavy16
+    else:
+        b = {"count_light": "light", "count_heavy": "heavy", "count_huge": "huge"}[dom]
+        c16 = work.get(f"cand_{b}_16", 0)
+        e16 = work.get(f"edges_{b}_16", 0)
+        r16 = work.get(f"rows_{b}_16", 0)
+        if b == "heavy" and heavy16 > 0:  # the 16-bit pivots ran in their own launch
+            algo_bytes = (4 * (work["cand_heavy"] - c16) + 8 * (work["edges_heavy"] - e16)
+                          + 8 * (work["rows_heavy"] - r16))
+            c16 = 0
+        else:
+            algo_bytes = (4 * (work[f"cand_{b}"] - c16) + 2 * c16 + 8 * work[f"edges_{b}"]
+                          + 8 * work[f"rows_{b}"])
+        dur_ms = stages[dom]
+    dur_s = dur_ms / 1e3
     achieved = algo_bytes / dur_s / 1e9 if dur_s > 0 else 0.0
     digest = source_digest(COUNT_SOURCES)
-    counters = counter_entry(dom, digest) or {}
-    kernel_names = {"count_light": "k_mid_wave", "count_heavy": "k_mid_block",
-                    "count_huge": "k_mid_block<true>"}
+    counters = counter_entry("count_heavy" if dom.startswith("count_heavy") else dom, digest) or {}
+    kernel_names = {"count_light": "k_mid_groups + k_mid_wave + k_mid_block (light stage)",
+                    "count_heavy": "k_mid_block (workgroup pivots: span bitmap / hash)",
+                    "count_heavy_bitmap16": "k_mid_block (workgroup pivots among the top 2^16 "
+                                            "ranks, 2048-word bitmap)",
+                    "count_huge": "k_mid_block<LK_GLOBAL>"}
     if work.get("algorithm") == 1:
         kernel_names = {"count_light": "k_count_light", "count_heavy": "k_count_heavy",
                         "count_huge": "k_count_heavy<true>"}
@@ -870,9 +898,10 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": counters.get("hbm_bytes_per_dispatch"),
         "algorithmic_bytes": int(algo_bytes),
+        "launch_ms": {k: round(v, 3) for k, v in launches.items()},
         "traffic_over_algorithmic": (round(counters["hbm_bytes_per_dispatch"] / algo_bytes, 3)
                                      if counters and algo_bytes else None),
-        "avg_ms": round(stages[dom], 3),
+        "avg_ms": round(dur_ms, 3),
         # fraction of cycles the SIMDs issued vector ALU work, from the same
         # counter summary (null when it is stale)
         "valu_busy": counters.get("valu_busy"),

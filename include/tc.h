@@ -453,9 +453,12 @@ tc_status tc_top_k(const tc_graph *g, int32_t k, int32_t *vertices, double *valu
  *   pivot reads the candidates of pivots among the top 2^16 ranks as 16-bit
  *   entries (rank less n - 2^16) in its wavefront and workgroup kernels;
  *   TC_STAT_CAND_HEAVY_16 is the part of the heavy bin's candidates read so
- *   (0 after the low pivot).
+ *   (0 after the low pivot), and TC_STAT_EDGES_HEAVY_16 / _ROWS_HEAVY_16
+ *   the pairs and pivots they belong to: the work of the launch timed as
+ *   TC_STAGE_COUNT_HEAVY_BITMAP16 when the tuning's bitmap has at least
+ *   2048 words.
  * ---------------------------------------------------------------------- */
-#define TC_NUM_STAGES 10
+#define TC_NUM_STAGES 14
 enum {
     TC_STAGE_CSR_BUILD = 0,   /* dedup, degrees, symmetric row offsets  */
     TC_STAGE_DEGREE_RANK = 1, /* degree ordering                        */
@@ -468,16 +471,24 @@ enum {
     TC_STAGE_FOLD = 7,        /* bit-matrix fold (middle pivot only)    */
     TC_STAGE_TRI = 8,         /* support per edge, tri(v), triG (after
                                  the low pivot: + symmetric adjacency)   */
-    TC_STAGE_AGGREGATE = 9    /* Algorithm 2 sums + quotient            */
+    TC_STAGE_AGGREGATE = 9,   /* Algorithm 2 sums + quotient            */
+    /* launches inside the two intersection stages above (middle pivot;
+       0 after the low pivot) */
+    TC_STAGE_COUNT_LIGHT_GROUPS = 10,   /* rows <= 128 entries, 16 lanes each */
+    TC_STAGE_COUNT_LIGHT_WAVE = 11,     /* other wavefront rows, LDS hash    */
+    TC_STAGE_COUNT_LIGHT_BITMAP = 12,   /* wavefront rows moved to a bitmap  */
+    TC_STAGE_COUNT_HEAVY_BITMAP16 = 13  /* workgroup rows among the top 2^16
+                                           ranks, 2048-word bitmap           */
 };
-#define TC_NUM_WORK_STATS 18
+#define TC_NUM_WORK_STATS 20
 enum {
     TC_STAT_N = 0, TC_STAT_M = 1, TC_STAT_MAX_DPLUS = 2,
     TC_STAT_ROWS_LIGHT = 3, TC_STAT_ROWS_HEAVY = 4, TC_STAT_ROWS_HUGE = 5,
     TC_STAT_CAND_LIGHT = 6, TC_STAT_CAND_HEAVY = 7, TC_STAT_CAND_HUGE = 8,
     TC_STAT_MERGE_WORK = 9, TC_STAT_WEDGES = 10, TC_STAT_TRIANGLES = 11,
     TC_STAT_EDGES_LIGHT = 12, TC_STAT_EDGES_HEAVY = 13, TC_STAT_EDGES_HUGE = 14,
-    TC_STAT_W_HASH = 15, TC_STAT_ALGORITHM = 16, TC_STAT_CAND_HEAVY_16 = 17
+    TC_STAT_W_HASH = 15, TC_STAT_ALGORITHM = 16, TC_STAT_CAND_HEAVY_16 = 17,
+    TC_STAT_EDGES_HEAVY_16 = 18, TC_STAT_ROWS_HEAVY_16 = 19
 };
 
 tc_status tc_set_profiling(int32_t on);

@@ -671,12 +671,14 @@ tc_status tc_set_profiling(int32_t on) {
 tc_status tc_get_stage_ms(const tc_graph *g, double *ms) {
     if (!g || !ms) return TC_ERR_INVALID_ARG;
     if (!g->prof_build && !g->prof_compute) return TC_ERR_NOT_COMPUTED;
-    static const int from[TC_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7, 8, 9, 10};
-    static const int to[TC_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8, 9, 10, 11};
+    static const int from[TC_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7, 8, 9, 10, 5, 12, 13, 6};
+    static const int to[TC_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13, 6, 14};
     for (int i = 0; i < TC_NUM_STAGES; ++i) {
         ms[i] = 0.0;
         bool build = to[i] <= 3;
         if ((build && !g->prof_build) || (!build && !g->prof_compute)) continue;
+        // launches of the middle pivot's count: none after the low pivot
+        if (i >= TC_STAGE_COUNT_LIGHT_GROUPS && g->algo_used == TC_ALGO_LOW_PIVOT) continue;
         hipEvent_t a = g->prof_ev[from[i]], b = g->prof_ev[to[i]];
         if (!a || !b) continue;
         TC_HIP(hipEventSynchronize(b));

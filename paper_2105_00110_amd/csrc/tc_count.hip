@@ -337,6 +337,7 @@ tc_status tc_count(tc_graph *g, const tc_tuning *tin, hipStream_t s) {
         g->light_max = t.light_max_dplus;
         g->huge_min = 0x7FFFFFFF;
         for (int k = 5; k <= 9; ++k) tc_prof_mark(g, k, s);
+        for (int k = 12; k <= 14; ++k) tc_prof_mark(g, k, s);
         return TC_OK;
     }
 
@@ -470,8 +471,8 @@ tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s) {
     if (g->n == 0 || g->m == 0) return TC_OK;
     tc_scratch tmp(s);
     unsigned long long *acc = nullptr;
-    TC_TRY(tmp.get(&acc, 13));
-    TC_HIP(hipMemsetAsync(acc, 0, 13 * sizeof(unsigned long long), s));
+    TC_TRY(tmp.get(&acc, 15));
+    TC_HIP(hipMemsetAsync(acc, 0, 15 * sizeof(unsigned long long), s));
     int light_max = g->light_max > 0 ? g->light_max : 64;
     int huge_min = g->huge_min > 0 ? g->huge_min : 0x7FFFFFFF;
     const bool mid = g->algo_used != TC_ALGO_LOW_PIVOT;
@@ -480,7 +481,7 @@ tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s) {
                                                acc);
     TC_LAUNCHED();
     if (mid) TC_TRY(tc_mid_stats(g, acc, s));
-    unsigned long long h[13];
+    unsigned long long h[15];
     uint64_t tri = 0;
     TC_HIP(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
     if (g->triG) TC_HIP(hipMemcpyAsync(&tri, g->triG + g->num_graphs, 8, hipMemcpyDeviceToHost, s));
@@ -500,5 +501,7 @@ tc_status tc_work_stats(tc_graph *g, int64_t *stats, hipStream_t s) {
     stats[TC_STAT_W_HASH] = (int64_t)h[11];
     stats[TC_STAT_ALGORITHM] = mid ? TC_ALGO_MID_PIVOT : TC_ALGO_LOW_PIVOT;
     stats[TC_STAT_CAND_HEAVY_16] = (int64_t)h[12];
+    stats[TC_STAT_EDGES_HEAVY_16] = (int64_t)h[13];
+    stats[TC_STAT_ROWS_HEAVY_16] = (int64_t)h[14];
     return TC_OK;
 }

@@ -129,11 +129,11 @@ __global__ void k_in_len(int32_t n, const int32_t *__restrict__ perm,
 __global__ void k_item_count(int32_t n, const int64_t *__restrict__ orp,
                              const int32_t *__restrict__ ocol, const int64_t *__restrict__ in_ptr,
                              int lo, int hi, int S, int sel, int64_t span_max, int64_t pairs_min,
-                             uint32_t *__restrict__ cnt) {
+                             int32_t rlo, int32_t rhi, uint32_t *__restrict__ cnt) {
     GRID_STRIDE(v, n) {
         const int64_t d = orp[v + 1] - orp[v];
         const int64_t in = in_ptr[v + 1] - in_ptr[v];
-        bool ok = d >= lo && d <= hi && in > 0;
+        bool ok = d >= lo && d <= hi && in > 0 && v >= rlo && v < rhi;
         if (ok && sel != 0) {
             const int64_t span = (int64_t)ocol[orp[v + 1] - 1] - ocol[orp[v]] + 1;
             const bool fits = span <= span_max && in >= pairs_min;
@@ -577,11 +577,10 @@ __global__ __launch_bounds__(256, 4) void k_mid_groups(const int64_t *__restrict
 }
 
 // One workgroup per item; its wavefronts share the pivot's lookup structure
-// and take the item's 64-pair groups in turn.  With wide16 (the workgroup
-// pivots' launch) pivots among the top 2^16 ranks use LK_BITMAP16 when the
-// bitmap has room for its 2048 words; short items (the wavefront pivots
-// moved here) keep the bitmap over their row's span, which is cheaper to
-// build.
+// and take the item's 64-pair groups in turn.  With wide16 (the launch of
+// the workgroup pivots among the top 2^16 ranks, bitmap_words = 2048) they
+// use LK_BITMAP16; short items (the wavefront pivots moved here) keep the
+// bitmap over their row's span, which is cheaper to build.
 template <int LK>
 __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ orp,
                                                     const int32_t *__restrict__ ocol,
@@ -1052,8 +1051,9 @@ __global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
                             const int32_t *__restrict__ ocol, const uint64_t *__restrict__ in_pair,
                             int light_max, int huge_min, int32_t r16,
                             unsigned long long *__restrict__ acc) {
-    // cand per bin, pairs per bin, heavy cand read as 16-bit entries
-    unsigned long long sums[7] = {0, 0, 0, 0, 0, 0, 0};
+    // cand per bin, pairs per bin, heavy cand and pairs of pivots among the
+    // top 2^16 ranks
+    unsigned long long sums[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     GRID_STRIDE(i, m) {
         const uint64_t pr = in_pair[i];
         const uint32_t k = (uint32_t)pr;
@@ -1065,21 +1065,25 @@ __global__ void k_mid_stats(int64_t m, const int64_t *__restrict__ orp,
         const int bin = d <= light_max ? 0 : (d < huge_min ? 1 : 2);
         sums[bin] += (unsigned long long)len;
         sums[3 + bin] += 1ull;
-        if (bin == 1 && v >= r16) sums[6] += (unsigned long long)len;
+        if (bin == 1 && v >= r16) {
+            sums[6] += (unsigned long long)len;
+            sums[7] += 1ull;
+        }
     }
 #pragma unroll
-    for (int b = 0; b < 7; ++b) {
+    for (int b = 0; b < 8; ++b) {
         const unsigned long long v = tc_wave_sum(sums[b]);
-        if (__lane_id() == 0 && v) atomicAdd(&acc[b < 3 ? 3 + b : (b < 6 ? 5 + b : 12)], v);
+        if (__lane_id() == 0 && v) atomicAdd(&acc[b < 3 ? 3 + b : (b < 6 ? 5 + b : 6 + b)], v);
     }
 }
 
 __global__ void k_mid_pivots(int32_t n, const int64_t *__restrict__ orp,
                              const int64_t *__restrict__ in_ptr, int light_max, int huge_min,
-                             unsigned long long *__restrict__ acc) {
-    // per-thread bin counts, summed over the wavefront: three atomics per
-    // wavefront instead of one per pivot on the same three words
-    unsigned long long c[3] = {0, 0, 0};
+                             int32_t r16, unsigned long long *__restrict__ acc) {
+    // per-thread bin counts (and heavy pivots among the top 2^16 ranks),
+    // summed over the wavefront: four atomics per wavefront instead of one
+    // per pivot on the same four words
+    unsigned long long c[4] = {0, 0, 0, 0};
     GRID_STRIDE(v, n) {
         const int64_t d = orp[v + 1] - orp[v];
         if (d < 1 || in_ptr[v + 1] == in_ptr[v]) continue;
@@ -1087,11 +1091,12 @@ __global__ void k_mid_pivots(int32_t n, const int64_t *__restrict__ orp,
         c[0] += bin == 0;
         c[1] += bin == 1;
         c[2] += bin == 2;
+        c[3] += bin == 1 && v >= r16;
     }
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
+    for (int b = 0; b < 4; ++b) {
         const unsigned long long t = tc_wave_sum(c[b]);
-        if (__lane_id() == 0 && t) atomicAdd(&acc[b], t);
+        if (__lane_id() == 0 && t) atomicAdd(&acc[b < 3 ? b : 14], t);
     }
 }
 
@@ -1101,6 +1106,7 @@ __global__ void k_mid_pivots(int32_t n, const int64_t *__restrict__ orp,
 struct ItemPlan {
     int lo = 1, hi = 0, S = 64, sel = 0;
     int64_t span_max = 0, pairs_min = 0;
+    int32_t rlo = 0, rhi = 0x7FFFFFFF;  // pivot ranks [rlo, rhi)
     uint32_t *cnt = nullptr, *off = nullptr;
     int64_t count = 0;
     int32_t *item_v = nullptr;
@@ -1113,7 +1119,7 @@ tc_status plan_count(const tc_graph *g, ItemPlan &p, uint32_t *tot, tc_scratch &
     TC_TRY(keep.get(&p.cnt, n));
     TC_TRY(keep.get(&p.off, n));
     k_item_count<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->ocol, g->in_ptr, p.lo, p.hi, p.S, p.sel,
-                                            p.span_max, p.pairs_min, p.cnt);
+                                            p.span_max, p.pairs_min, p.rlo, p.rhi, p.cnt);
     TC_LAUNCHED();
     return tc_scan_u32(p.cnt, p.off, n, tot, s);
 }
@@ -1248,13 +1254,21 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     // 64 / GROUP_LANES to a wavefront, in items of at most GROUP_PAIRS pairs
     const int gmax = light_max < GROUP_DMAX ? light_max : GROUP_DMAX;
     const int group_pairs = wave_pairs < GROUP_PAIRS ? wave_pairs : GROUP_PAIRS;
-    enum { P_GROUP, P_WAVE, P_LBITMAP, P_BITMAP, P_BLOCK, P_HUGE, P_ZERO, NPLANS };
+    enum { P_GROUP, P_WAVE, P_LBITMAP, P_BITMAP16, P_BITMAP, P_BLOCK, P_HUGE, P_ZERO, NPLANS };
     ItemPlan pl[NPLANS];
     pl[P_GROUP] = {1, gmax, group_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs};
     pl[P_WAVE] = {gmax + 1, light_max, wave_pairs, 2 * lsplit, span_max, t.light_bitmap_pairs};
     pl[P_LBITMAP] = {1, lsplit ? light_max : 0, block_pairs, 1, span_max, t.light_bitmap_pairs};
-    pl[P_BITMAP] = {light_max + 1, split ? huge_min - 1 : light_max, block_pairs, 1, span_max, 0};
-    pl[P_BLOCK] = {light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, 0};
+    // workgroup pivots among the top 2^16 ranks take the 2048-word bitmap
+    // over 16-bit values whatever their span (when the tuning allows that
+    // many words), in a launch of their own whose smaller LDS footprint
+    // keeps more wavefronts resident; the others take the span bitmap or
+    // hash
+    const int32_t r16s = bw >= BITMAP16_WORDS ? g->rank16_base : 0x7FFFFFFF;
+    pl[P_BITMAP16] = {light_max + 1, huge_min - 1, block_pairs, 0, 0, 0, r16s, 0x7FFFFFFF};
+    pl[P_BITMAP] = {light_max + 1, split ? huge_min - 1 : light_max, block_pairs, 1, span_max, 0,
+                    0, r16s};
+    pl[P_BLOCK] = {light_max + 1, huge_min - 1, block_pairs, 2 * split, span_max, 0, 0, r16s};
     pl[P_HUGE] = {huge_min, 0x7FFFFFFF, block_pairs, 0, 0, 0};
     // pivots with an empty row: their pairs' bit rows are only cleared
     pl[P_ZERO] = {0, 0, wave_pairs, 0, 0, 0};
@@ -1283,6 +1297,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     const int64_t n_group = pl[P_GROUP].count;
     const int64_t n_wave = pl[P_WAVE].count, n_lbitmap = pl[P_LBITMAP].count;
     const int64_t n_bitmap = pl[P_BITMAP].count, n_block = pl[P_BLOCK].count;
+    const int64_t n_bitmap16 = pl[P_BITMAP16].count;
     const int64_t n_huge = pl[P_HUGE].count;
     int32_t *wv_v = pl[P_WAVE].item_v, *lb_v = pl[P_LBITMAP].item_v, *bm_v = pl[P_BITMAP].item_v;
     int32_t *bl_v = pl[P_BLOCK].item_v, *hu_v = pl[P_HUGE].item_v;
@@ -1290,7 +1305,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
     uint32_t *bm_f = pl[P_BITMAP].item_first, *bl_f = pl[P_BLOCK].item_first;
     uint32_t *hu_f = pl[P_HUGE].item_first;
     g->n_light = n_group + n_wave + n_lbitmap;
-    g->n_heavy = n_block + n_bitmap;
+    g->n_heavy = n_block + n_bitmap + n_bitmap16;
     g->n_huge = n_huge;
     // pairs whose pivot closes nothing are never scanned: their rows are
     // cleared, and every other word is written by the count
@@ -1312,6 +1327,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
             pl[P_GROUP].item_first, n_group, gmax, group_pairs, g->osup, found);
         TC_LAUNCHED();
     }
+    tc_prof_mark(g, 12, s);
     if (n_wave > 0) {
         const size_t per_wave = mid_wave_bytes(light_max);
         int wpb = t.light_block / TC_WAVE;
@@ -1323,6 +1339,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
             light_max, wave_pairs, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
+    tc_prof_mark(g, 13, s);
     if (n_lbitmap > 0) {
         const size_t lds = mid_block_bytes(light_max, wpb_block, LK_BITMAP, bw);
         int64_t blocks = n_lbitmap < 1048576 ? n_lbitmap : 1048576;
@@ -1332,13 +1349,24 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 6, s);
+    if (n_bitmap16 > 0) {
+        const int hmax = g->max_dplus < huge_min - 1 ? g->max_dplus : huge_min - 1;
+        const size_t lds = mid_block_bytes(hmax, wpb_block, LK_BITMAP, BITMAP16_WORDS);
+        int64_t blocks = n_bitmap16 < 1048576 ? n_bitmap16 : 1048576;
+        k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
+            g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, pl[P_BITMAP16].item_v,
+            pl[P_BITMAP16].item_first, n_bitmap16, hmax, block_pairs, BITMAP16_WORDS, 1, g->ocol16,
+            g->rank16_base, g->osup, found);
+        TC_LAUNCHED();
+    }
+    tc_prof_mark(g, 14, s);
     if (n_bitmap > 0) {
         const int hmax = g->max_dplus < huge_min - 1 ? g->max_dplus : huge_min - 1;
         const size_t lds = mid_block_bytes(hmax, wpb_block, LK_BITMAP, bw);
         int64_t blocks = n_bitmap < 1048576 ? n_bitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, bm_v, bm_f, n_bitmap,
-            hmax, block_pairs, bw, 1, g->ocol16, g->rank16_base, g->osup, found);
+            hmax, block_pairs, bw, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     if (n_block > 0) {
@@ -1409,7 +1437,7 @@ tc_status tc_mid_stats(tc_graph *g, unsigned long long *acc, hipStream_t s) {
                                              huge_min, r16, acc);
     TC_LAUNCHED();
     const unsigned pg = grid_for(g->n) < 4096u ? grid_for(g->n) : 4096u;
-    k_mid_pivots<<<pg, BK, 0, s>>>(g->n, g->orp, g->in_ptr, light_max, huge_min, acc);
+    k_mid_pivots<<<pg, BK, 0, s>>>(g->n, g->orp, g->in_ptr, light_max, huge_min, r16, acc);
     TC_LAUNCHED();
     return TC_OK;
 }

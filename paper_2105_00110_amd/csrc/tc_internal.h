@@ -8,7 +8,7 @@
 #include "tc.h"
 
 #define TC_WAVE 64
-#define TC_PROF_MARKS 12
+#define TC_PROF_MARKS 15
 #define TC_OCOL_PAD 64
 
 // ---------------------------------------------------------------------------

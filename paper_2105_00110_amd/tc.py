@@ -108,11 +108,14 @@ _SIGS = {
     "tc_get_work_stats": (_st, [_vp, _vp, _vp]),
 }
 
+# the last four are launches inside count_light and count_heavy
 STAGES = ["csr_build", "degree_rank", "orient", "bin", "count_light", "count_heavy",
-          "count_huge", "fold", "tri", "aggregate"]
+          "count_huge", "fold", "tri", "aggregate", "count_light_groups", "count_light_wave",
+          "count_light_bitmap", "count_heavy_bitmap16"]
 WORK_STATS = ["n", "m", "max_dplus", "rows_light", "rows_heavy", "rows_huge", "cand_light",
               "cand_heavy", "cand_huge", "merge_work", "wedges", "triangles", "edges_light",
-              "edges_heavy", "edges_huge", "w_hash", "algorithm", "cand_heavy_16"]
+              "edges_heavy", "edges_huge", "w_hash", "algorithm", "cand_heavy_16",
+              "edges_heavy_16", "rows_heavy_16"]
 
 
 def load(path=None):

@@ -163,6 +163,37 @@ def test_every_bin_runs(tclib, algo):
     assert_parity(res, ref)
 
 
+@pytest.mark.parametrize("algo", [1, 2])
+def test_launch_times_and_heavy_16_statistics(tclib, algo):
+    # the middle pivot's count launches are timed one by one inside their
+    # stages, and the work statistics of the 16-bit workgroup launch are a
+    # part of the heavy bin's (all of it when n <= 2^16); the low pivot
+    # reports no such launches
+    src, dst, n = gg.rmat(16, 16, seed=16)
+    tuning = {"algorithm": algo, "light_max_dplus": 64}
+    tclib.tc_set_profiling(True)
+    try:
+        g = tclib.Graph.from_edges(src, dst, n)
+        g.compute(tuning)
+        ms = g.stage_ms()
+        ws = g.work_stats()
+        g.close()
+    finally:
+        tclib.tc_set_profiling(False)
+    _say("launch times", algo, {k: round(v, 3) for k, v in ms.items()})
+    sub = ms["count_light_groups"] + ms["count_light_wave"] + ms["count_light_bitmap"]
+    if algo == 1:
+        assert sub == 0.0 and ms["count_heavy_bitmap16"] == 0.0
+        assert ws["cand_heavy_16"] == ws["edges_heavy_16"] == ws["rows_heavy_16"] == 0
+        return
+    assert abs(sub - ms["count_light"]) <= 0.02 + 0.02 * ms["count_light"]
+    assert 0.0 < ms["count_heavy_bitmap16"] <= ms["count_heavy"] + 0.02
+    # n = 2^16: every pivot is among the top 2^16 ranks
+    assert ws["rows_heavy"] > 0
+    assert (ws["cand_heavy_16"], ws["edges_heavy_16"], ws["rows_heavy_16"]) == \
+        (ws["cand_heavy"], ws["edges_heavy"], ws["rows_heavy"])
+
+
 @pytest.mark.parametrize("n", [65536, 65537, 70000])
 def test_sixteen_bit_candidates_at_the_base(tclib, n):
     # the middle pivot reads the candidates of pivots among the top 2^16
