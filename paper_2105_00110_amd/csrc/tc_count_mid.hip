@@ -254,6 +254,52 @@ __device__ void bitmap_build(uint2 *bm, uint32_t *scan, const int32_t *__restric
     __syncthreads();
 }
 
+// One lane's 32-entry run of a pair's tail for an LK_BITMAP16 pivot: the
+// hit mask of entries c0 .. c0 + cnt - 1 (bit j for entry c0 + j).  17
+// aligned words hold the 32 entries from c0 (an odd c0 starts in the upper
+// half of the first); each aligned pair is probed as loaded: the lower entry
+// is the word's low 16 bits, whose low 5 bits the bit-field reads take as
+// they are, the upper entry its high 16 bits.  Every hit adds 1 to the
+// counter of its place in the pivot's row; an entry past the tail adds its
+// bit to the lane's spare counter, which is never read.
+__device__ __forceinline__ uint32_t bitmap16_run(const uint16_t *__restrict__ ocol16, int64_t c0,
+                                                 int cnt, const uint2 *bm, uint32_t *lsup,
+                                                 int spare) {
+    const uint32_t *o32 = reinterpret_cast<const uint32_t *>(ocol16);
+    const int64_t q = c0 >> 1;
+    const uint32_t sh = (uint32_t)(c0 & 1) << 4;
+    uint32_t dw[17];
+#pragma unroll
+    for (int j = 0; j < 17; ++j) dw[j] = o32[q + j];
+    uint32_t pk[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) pk[j] = __builtin_amdgcn_alignbit(dw[j + 1], dw[j], sh);
+    uint32_t mask = 0;
+#pragma unroll
+    for (int c = 0; c < 16; c += 4) {
+        uint32_t key[8];
+        uint2 w[8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            key[2 * e] = pk[c + e];
+            key[2 * e + 1] = pk[c + e] >> 16;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[e] = bm[__builtin_amdgcn_ubfe(key[e], 5u, 11u)];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 2 * c + e;  // the entry's place in the run
+            const uint32_t bit = __builtin_amdgcn_ubfe(w[e].x, key[e], 1u);
+            const uint32_t at =
+                w[e].y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w[e].x, 0u, key[e]));
+            atomicAdd(&lsup[bit != 0u && k < cnt ? (int)at : spare], bit);
+            mask |= bit << k;
+        }
+    }
+    if (cnt < 32) mask &= (1u << cnt) - 1u;
+    return mask;
+}
+
 // ---------------------------------------------------------------------------
 // One 64-pair group of pivot v (wave-level).  Pairs g0 .. gend-1 (at most
 // 64).  gx/gs/gb/gt: this wavefront's LDS arrays (exclusive scan of word
@@ -317,51 +363,6 @@ __device__ __forceinline__ void mid_group(const int32_t *__restrict__ ocol,
             const int64_t kw = x - gx[p];
             const int64_t c0 = gs[p] + 32 * kw;
             const int cnt = min(32, gt[p] - 32 * (int)kw);
-            if constexpr (LK == LK_BITMAP16) {
-                // 17 aligned words hold the 32 entries from c0 (an odd c0
-                // starts in the upper half of the first); each aligned pair
-                // is probed as loaded: the lower entry is the word's low 16
-                // bits, whose low 5 bits the bit-field reads take as they
-                // are, the upper entry its high 16 bits
-                const uint32_t *o32 = reinterpret_cast<const uint32_t *>(ocol16);
-                const int64_t q = c0 >> 1;
-                const uint32_t sh = (uint32_t)(c0 & 1) << 4;
-                uint32_t dw[17];
-#pragma unroll
-                for (int j = 0; j < 17; ++j) dw[j] = o32[q + j];
-                uint32_t pk[16];
-#pragma unroll
-                for (int j = 0; j < 16; ++j) pk[j] = __builtin_amdgcn_alignbit(dw[j + 1], dw[j], sh);
-                const int spare = dv + lane;
-                uint32_t mask = 0;
-#pragma unroll
-                for (int c = 0; c < 16; c += 4) {
-                    uint32_t key[8];
-                    uint2 w[8];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        key[2 * e] = pk[c + e];
-                        key[2 * e + 1] = pk[c + e] >> 16;
-                    }
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) w[e] = bmr.bm[__builtin_amdgcn_ubfe(key[e], 5u, 11u)];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int k = 2 * c + e;  // the entry's place in the run
-                        const uint32_t bit = __builtin_amdgcn_ubfe(w[e].x, key[e], 1u);
-                        const uint32_t at =
-                            w[e].y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w[e].x, 0u, key[e]));
-                        // an entry past the tail adds its bit to the spare
-                        // counter, which is never read
-                        atomicAdd(&lsup[bit != 0u && k < cnt ? (int)at : spare], bit);
-                        mask |= bit << k;
-                    }
-                }
-                if (cnt < 32) mask &= (1u << cnt) - 1u;
-                bits[gb[p] + kw] = mask;
-                found += (unsigned long long)__popc(mask);
-                continue;
-            }
             // whole 32-entry run (the arrays are padded past their end);
             // entries past the tail are masked to EMPTY
             uint32_t ww[32];
@@ -577,10 +578,10 @@ __global__ __launch_bounds__(256, 4) void k_mid_groups(const int64_t *__restrict
 }
 
 // One workgroup per item; its wavefronts share the pivot's lookup structure
-// and take the item's 64-pair groups in turn.  With wide16 (the launch of
-// the workgroup pivots among the top 2^16 ranks, bitmap_words = 2048) they
-// use LK_BITMAP16; short items (the wavefront pivots moved here) keep the
-// bitmap over their row's span, which is cheaper to build.
+// and take the item's 64-pair groups in turn.  Pivots among the top 2^16
+// ranks scan 16-bit entries; short items (the wavefront pivots moved to
+// LK_BITMAP) take the bitmap over their row's span, which is cheaper to
+// build than the 2048-word one of k_mid_block16.
 template <int LK>
 __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ orp,
                                                     const int32_t *__restrict__ ocol,
@@ -591,7 +592,7 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ item_v,
                                                     const uint32_t *__restrict__ item_first,
                                                     int64_t nitems, int dmax, int item_pairs,
-                                                    int bitmap_words, int wide16,
+                                                    int bitmap_words,
                                                     const uint16_t *__restrict__ ocol16, int32_t r16,
                                                     uint32_t *__restrict__ osup,
                                                     unsigned long long *__restrict__ tri_total) {
@@ -644,30 +645,13 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
             __syncthreads();
         } else if constexpr (LK == LK_BITMAP) {
             for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
-            if (n16 && wide16 && bitmap_words >= BITMAP16_WORDS) {
-                // LK_BITMAP16: 2048 words over the 16-bit values, that is
-                // ranks rel .. rel + 2^16 - 1
-                bmr.span = 32u * BITMAP16_WORDS;
-                bitmap_build(bm, scan, ocol, vstart, d, rel, bmr.span);
-                bmr.lo = 0;
-            } else {
-                const uint32_t lo = (uint32_t)ocol[vstart];
-                bmr.span = (uint32_t)ocol[vstart + d - 1] - lo + 1;
-                bitmap_build(bm, scan, ocol, vstart, d, lo, bmr.span);
-                bmr.lo = lo - rel;
-            }
+            const uint32_t lo = (uint32_t)ocol[vstart];
+            bmr.span = (uint32_t)ocol[vstart + d - 1] - lo + 1;
+            bitmap_build(bm, scan, ocol, vstart, d, lo, bmr.span);
+            bmr.lo = lo - rel;
         }
         const uint32_t hmax = (uint32_t)ocol[vstart + d - 1] - rel;
         for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE) {
-            if constexpr (LK == LK_BITMAP) {
-                if (n16 && wide16 && bitmap_words >= BITMAP16_WORDS) {
-                    mid_group<LK_BITMAP16, TC_WAVE, true>(ocol, ocol16, in_pair, rowinfo, g0,
-                                                          min(g0 + TC_WAVE, pend), t, bmr, hmax,
-                                                          lsup, vstart, d, gx, gs, gb, gt, bits,
-                                                          osup, found);
-                    continue;
-                }
-            }
             if constexpr (LK != LK_GLOBAL) {
                 if (n16) {
                     mid_group<LK, TC_WAVE, true>(ocol, ocol16, in_pair, rowinfo, g0,
@@ -676,8 +660,8 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
                     continue;
                 }
             }
-            mid_group<LK>(ocol, nullptr, in_pair, rowinfo, g0, min(g0 + TC_WAVE, pend), t,
-                          bmr, hmax, lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
+            mid_group<LK>(ocol, nullptr, in_pair, rowinfo, g0, min(g0 + TC_WAVE, pend), t, bmr,
+                          hmax, lsup, vstart, d, gx, gs, gb, gt, bits, osup, found);
         }
         if constexpr (LK != LK_GLOBAL) {
             __syncthreads();
@@ -687,6 +671,101 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
             }
             __syncthreads();
         }
+    }
+    found = tc_wave_sum(found);
+    if (lane == 0 && found) atomicAdd(tri_total, found);
+}
+
+// LDS bytes of k_mid_block16: the 2048-word bitmap, the pivot's counters
+// and the bitmap build's per-wavefront sums.
+__host__ __device__ __forceinline__ size_t mid_block16_bytes(int dmax) {
+    return 8 * (size_t)BITMAP16_WORDS + counter_bytes(dmax) + 64;
+}
+
+// Workgroup pivots among the top 2^16 ranks (LK_BITMAP16).  One workgroup
+// per item as in k_mid_block, but a wavefront keeps its 64 pairs' word
+// offsets, scan starts, tails and bit-row bases in registers and finds a
+// word's pair by a search over lane shuffles, so the workgroup's LDS is the
+// bitmap and the counters alone; with at most 80 VGPRs, six wavefronts per
+// SIMD stay resident to cover the latency of the candidate loads.
+__global__ __launch_bounds__(1024, 6) void k_mid_block16(
+    const int64_t *__restrict__ orp, const int32_t *__restrict__ ocol,
+    const int64_t *__restrict__ in_ptr, const uint64_t *__restrict__ in_pair,
+    const uint4 *__restrict__ rowinfo, uint32_t *__restrict__ bits,
+    const int32_t *__restrict__ item_v, const uint32_t *__restrict__ item_first, int64_t nitems,
+    int dmax, int item_pairs, const uint16_t *__restrict__ ocol16, int32_t r16,
+    uint32_t *__restrict__ osup, unsigned long long *__restrict__ tri_total) {
+    extern __shared__ uint4 lds4[];
+    char *base = reinterpret_cast<char *>(lds4);
+    uint2 *bm = reinterpret_cast<uint2 *>(base);
+    uint32_t *lsup = reinterpret_cast<uint32_t *>(base + 8 * (size_t)BITMAP16_WORDS);
+    uint32_t *scan = reinterpret_cast<uint32_t *>(base + 8 * (size_t)BITMAP16_WORDS +
+                                                  counter_bytes(dmax));
+    const int wpb = blockDim.x / TC_WAVE;
+    const int wv = threadIdx.x / TC_WAVE;
+    const int lane = __lane_id();
+    unsigned long long found = 0;
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int32_t v = item_v[it];
+        const int64_t first = item_first[it];
+        const int64_t pend = min(first + (int64_t)item_pairs, in_ptr[v + 1]);
+        const int64_t vstart = orp[v];
+        const int d = (int)(orp[v + 1] - vstart);
+        // 2048 words over the 16-bit values, that is ranks r16 .. r16 + 2^16 - 1
+        for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
+        bitmap_build(bm, scan, ocol, vstart, d, (uint32_t)r16, 32u * BITMAP16_WORDS);
+        const int spare = d + lane;
+        for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE) {
+            // this lane's pair: scan start, tail length, bit-row base and
+            // word count (a row below 2^16 entries has fewer than 2^11
+            // words per pair, so the group's word offsets fit 32 bits)
+            const int64_t i = g0 + lane;
+            int words = 0, tail = 0;
+            uint32_t start = 0;
+            int64_t gbase = 0;
+            if (i < pend) {
+                const uint64_t pr = in_pair[i];
+                const int64_t k = (int64_t)(uint32_t)pr;
+                const uint4 ri = rowinfo[(int32_t)(pr >> 32)];
+                const int64_t rs = ri.z;
+                const int64_t du = (int64_t)ri.w - rs;
+                const int64_t ii = k - rs;
+                tail = (int)(du - 1 - ii);
+                words = (tail + 31) >> 5;
+                start = (uint32_t)(k + 1);
+                gbase = (int64_t)(((uint64_t)ri.y << 32) | ri.x) + bit_words(du) - bit_words(du - ii);
+            }
+            const int incl = tc_wave_incl_scan(words);
+            const int excl = incl - words;
+            const int total = __shfl(incl, TC_WAVE - 1, TC_WAVE);
+            for (int wb = 0; wb < total; wb += TC_WAVE) {
+                const int x = wb + lane;
+                // the last pair p with excl(p) <= x: six steps, every lane
+                int p = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1) {
+                    const int e = __shfl(excl, p + step, TC_WAVE);
+                    if (e <= x) p += step;
+                }
+                const int kw = x - __shfl(excl, p, TC_WAVE);
+                const uint32_t st = __shfl(start, p, TC_WAVE);
+                const int tl = __shfl(tail, p, TC_WAVE);
+                const int64_t gb = __shfl(gbase, p, TC_WAVE);
+                if (x < total) {
+                    const int cnt = min(32, tl - 32 * kw);
+                    const uint32_t mask =
+                        bitmap16_run(ocol16, (int64_t)st + 32 * kw, cnt, bm, lsup, spare);
+                    bits[gb + kw] = mask;
+                    found += (unsigned long long)__popc(mask);
+                }
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < d; j += blockDim.x) {
+            const uint32_t c = lsup[j];
+            if (c) atomicAdd(&osup[vstart + j], c);
+        }
+        __syncthreads();
     }
     found = tc_wave_sum(found);
     if (lane == 0 && found) atomicAdd(tri_total, found);
@@ -1345,18 +1424,18 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_lbitmap < 1048576 ? n_lbitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, lb_v, lb_f, n_lbitmap,
-            light_max, block_pairs, bw, 0, g->ocol16, g->rank16_base, g->osup, found);
+            light_max, block_pairs, bw, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 6, s);
     if (n_bitmap16 > 0) {
         const int hmax = g->max_dplus < huge_min - 1 ? g->max_dplus : huge_min - 1;
-        const size_t lds = mid_block_bytes(hmax, wpb_block, LK_BITMAP, BITMAP16_WORDS);
+        const size_t lds = mid_block16_bytes(hmax);
         int64_t blocks = n_bitmap16 < 1048576 ? n_bitmap16 : 1048576;
-        k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
+        k_mid_block16<<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, pl[P_BITMAP16].item_v,
-            pl[P_BITMAP16].item_first, n_bitmap16, hmax, block_pairs, BITMAP16_WORDS, 1, g->ocol16,
-            g->rank16_base, g->osup, found);
+            pl[P_BITMAP16].item_first, n_bitmap16, hmax, block_pairs, g->ocol16, g->rank16_base,
+            g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 14, s);
@@ -1366,7 +1445,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_bitmap < 1048576 ? n_bitmap : 1048576;
         k_mid_block<LK_BITMAP><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, bm_v, bm_f, n_bitmap,
-            hmax, block_pairs, bw, 0, g->ocol16, g->rank16_base, g->osup, found);
+            hmax, block_pairs, bw, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     if (n_block > 0) {
@@ -1375,7 +1454,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_block < 1048576 ? n_block : 1048576;
         k_mid_block<LK_HASH><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, bl_v, bl_f, n_block, hmax,
-            block_pairs, 0, 0, g->ocol16, g->rank16_base, g->osup, found);
+            block_pairs, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 7, s);
@@ -1384,7 +1463,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         int64_t blocks = n_huge < 1048576 ? n_huge : 1048576;
         k_mid_block<LK_GLOBAL><<<(unsigned)blocks, wpb_block * TC_WAVE, lds, s>>>(
             g->orp, g->ocol, g->in_ptr, g->in_pair, g->rowinfo, g->hitbits, hu_v, hu_f, n_huge, 0,
-            block_pairs, 0, 0, g->ocol16, g->rank16_base, g->osup, found);
+            block_pairs, 0, g->ocol16, g->rank16_base, g->osup, found);
         TC_LAUNCHED();
     }
     tc_prof_mark(g, 8, s);
