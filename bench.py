@@ -128,7 +128,7 @@ PMC_PASSES = [
 # kernels of the summary: (short name, which of its launch shapes in launch
 # order, or None for all) -> stage
 COUNTER_KERNELS = [
-    ("k_mid_block<2>", 1, "count_heavy"), ("k_mid_block<2>", 0, "count_light_bitmap"),
+    ("k_mid_block16", None, "count_heavy"), ("k_mid_block<2>", None, "count_light_bitmap"),
     ("k_mid_wave", None, "count_light"), ("k_mid_groups<16>", None, "count_light_groups"),
     ("k_fold_big<int>", None, "fold_big"), ("k_fold<16>", None, "fold_small"),
     ("k_place_by_smaller", None, "orient_place_smaller"),

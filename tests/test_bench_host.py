@@ -25,14 +25,16 @@ def _write(path, rows):
 
 COPY = "__amd_rocclr_copyBuffer"
 MID = "void (anonymous namespace)::k_mid_block<2>(int, unsigned int const*)"
+MID16 = "(anonymous namespace)::k_mid_block16(int, unsigned int const*)"
 
 
 def test_counter_summary_rule_and_shapes(tmp_path):
     b = _bench()
     d = tmp_path / "pmc"
-    # dispatches: k_mid_block light shape (grid 100) first, heavy (grid 200)
-    # second, in two steps; then the 1 GiB copy (three dispatches)
-    disp = [(COPY, 4096, 0), (MID, 100, 1), (MID, 200, 2), (MID, 100, 3), (MID, 200, 4),
+    # dispatches: the light bitmap launch (grid 100) and the top-2^16
+    # workgroup launch (grid 200), in two steps; then the 1 GiB copy (three
+    # dispatches)
+    disp = [(COPY, 4096, 0), (MID, 100, 1), (MID16, 200, 2), (MID, 100, 3), (MID16, 200, 4),
             (COPY, 4096, 5), (COPY, 4096, 6), (COPY, 4096, 7)]
     p1, p2 = [], []
     for name, grid, i in disp:
@@ -58,14 +60,14 @@ def test_counter_summary_rule_and_shapes(tmp_path):
              for name, grid, _ in disp]
     _write(str(d / "ktrace" / "host" / "run_kernel_trace.csv"), trace)
     _write(str(d / "ktrace" / "host" / "run_kernel_stats.csv"),
-           [{"Name": MID, "AverageNs": 2_000_000}, {"Name": COPY, "AverageNs": 400_000}])
+           [{"Name": MID, "AverageNs": 1_000_000}, {"Name": MID16, "AverageNs": 3_000_000},
+            {"Name": COPY, "AverageNs": 400_000}])
     b.summarize_counters(str(d), out_dir=str(tmp_path))
     out = json.load(open(tmp_path / "counters_rmat_s24.json"))
     k = out["kernels"]
     assert out["copy_check"]["read_ratio"] == 1.0 and out["copy_check"]["write_ratio"] == 1.0
-    # the second launch shape of k_mid_block is the heavy one
-    assert k["count_heavy"]["kernel"] == "k_mid_block<2>@200"
-    assert k["count_light_bitmap"]["kernel"] == "k_mid_block<2>@100"
+    assert k["count_heavy"]["kernel"] == "k_mid_block16"
+    assert k["count_light_bitmap"]["kernel"] == "k_mid_block<2>"
     assert k["count_heavy"]["avg_ms"] == 3.0 and k["count_light_bitmap"]["avg_ms"] == 1.0
     # 32 B x 10 + 64 B x 20 + 128 B x the rest; 64 B x 100 + 32 B x 200
     h = k["count_heavy"]
