@@ -42,6 +42,7 @@
 namespace {
 
 constexpr int64_t FUSED_MAX_N = 65535;
+constexpr int FUSED_MW = 4;  // entries of each list per round of the count's merge
 constexpr int FUSED_RB = 8;
 constexpr int FUSED_RADIX = 1 << FUSED_RB;
 constexpr int FUSED_ITEMS = 8;          // keys per thread in a scatter tile
@@ -448,25 +449,43 @@ __device__ void fused_one_graph(const FusedArgs &a, int32_t g, FusedLds<BLOCK> &
         for (uint32_t q = tid; q <= n; q += BLOCK) orp[q] = 0;
     __syncthreads();
 
-    // count: the tail of N_H(r) after c against N_H(c)
+    // count: the tail of N_H(r) after c against N_H(c), merged four entries
+    // of each list at a time: the eight loads of a round are independent
+    // (one memory latency per round instead of one per step), all sixteen
+    // pairs are compared, and every entry up to the smaller of the two
+    // windows' last entries is then settled (an entry above it can equal
+    // nothing in the other window)
     for (uint32_t s = tid; s < m; s += BLOCK) {
         const uint32_t r = orow[s], c = ocol[s];
         uint32_t i = s + 1, j = orp[c];
         const uint32_t ie = orp[r + 1], je = orp[c + 1];
         uint32_t t = 0;
         while (i < ie && j < je) {
-            const uint32_t x = ocol[i], y = ocol[j];
-            if (x < y) {
-                ++i;
-            } else if (y < x) {
-                ++j;
-            } else {
-                wg_add(&osup[i], 1u);
-                wg_add(&osup[j], 1u);
-                ++t;
-                ++i;
-                ++j;
+            uint32_t x[FUSED_MW], y[FUSED_MW];
+#pragma unroll
+            for (int e = 0; e < FUSED_MW; ++e) x[e] = i + e < ie ? ocol[i + e] : 0xFFFFFFFFu;
+#pragma unroll
+            for (int e = 0; e < FUSED_MW; ++e) y[e] = j + e < je ? ocol[j + e] : 0xFFFFFFFEu;
+            const uint32_t lim = x[FUSED_MW - 1] < y[FUSED_MW - 1] ? x[FUSED_MW - 1] : y[FUSED_MW - 1];
+            uint32_t na = 0, nb = 0;
+#pragma unroll
+            for (int e = 0; e < FUSED_MW; ++e) {
+                na += x[e] <= lim ? 1u : 0u;
+                nb += y[e] <= lim ? 1u : 0u;
             }
+#pragma unroll
+            for (int e = 0; e < FUSED_MW; ++e) {
+                int f = -1;  // the other window's entry equal to x[e], if any
+#pragma unroll
+                for (int q = 0; q < FUSED_MW; ++q) f = x[e] == y[q] ? q : f;
+                if (f >= 0) {
+                    wg_add(&osup[i + e], 1u);
+                    wg_add(&osup[j + f], 1u);
+                    ++t;
+                }
+            }
+            i += na;
+            j += nb;
         }
         if (t) wg_add(&osup[s], t);
     }
