@@ -42,7 +42,7 @@
 namespace {
 
 constexpr int64_t FUSED_MAX_N = 65535;
-constexpr int FUSED_MW = 4;  // entries of each list per round of the count's merge
+constexpr int FUSED_MW = 8;  // entries of each list per round of the count's merge
 constexpr int FUSED_RB = 8;
 constexpr int FUSED_RADIX = 1 << FUSED_RB;
 constexpr int FUSED_ITEMS = 8;          // keys per thread in a scatter tile
