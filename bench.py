@@ -124,6 +124,9 @@ PMC_PASSES = [
      "GRBM_GUI_ACTIVE"],
     ["TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_HIT_sum", "TCC_MISS_sum", "SQ_INSTS_LDS",
      "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS", "SQ_INSTS_VMEM_RD"],
+    # the requests the L2 sends on to DRAM, beside all of its requests (a
+    # request the MALL serves would show as the difference)
+    ["TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_WRREQ_DRAM_sum", "TCC_EA0_RDREQ_sum", "TCC_EA0_WRREQ_sum"],
 ]
 # kernels of the summary: (short name, which of its launch shapes in launch
 # order, or None for all) -> stage
@@ -248,8 +251,10 @@ def summarize_counters(d, out_dir=None):
                 round(tot("SQ_LDS_BANK_CONFLICT") / lds_active, 3) if lds_active else None,
             "vmem_rd_insts": int(tot("SQ_INSTS_VMEM_RD")),
             "tcc_hit_rate": round(hit / (hit + miss), 3) if hit + miss else None,
+            "rdreq_dram_fraction": round(tot("TCC_EA0_RDREQ_DRAM_sum") / rd, 4) if rd else None,
+            "wrreq_dram_fraction": round(tot("TCC_EA0_WRREQ_DRAM_sum") / wr, 4) if wr else None,
             "gpu_cycles_per_xcd": int(gui / 8),
-            "dispatches": sum(len(per[k]) for k in keys) // len(PMC_PASSES),
+            "dispatches": sum(1 for k in keys for (i, _) in per[k] if i == 0),
         }
         kernels[stage] = e
     for stage, e in kernels.items():
@@ -290,17 +295,23 @@ def summarize_counters(d, out_dir=None):
              "takes 128-byte fills from TCC_BUBBLE and prices every other request at 64 B.",
              f"- 1 GiB device-to-device copy: counted read / true = "
              f"{check['read_ratio'] if check else 'n/a'}, counted written / true = "
-             f"{check['write_ratio'] if check else 'n/a'}.", "",
+             f"{check['write_ratio'] if check else 'n/a'}.",
+             "- The DRAM share is TCC_EA0_RDREQ_DRAM / TCC_EA0_RDREQ (and the same for writes). "
+             "A share of 1 means the counter reports every L2 miss as a DRAM request, so on this "
+             "device it cannot tell requests the 256 MB MALL serves from those HBM serves: the "
+             "bytes above are L2-miss bytes, which can run above the copy rate.", "",
              "## Per kernel (mean per dispatch)", "",
              "| stage | kernel | ms | read GB | reads 128 B / 64 B / 32 B (M) | write GB | "
-             "HBM GB/s | VALU busy | L2 hit | LDS conflicts / active LDS cycle |",
-             "|---|---|---:|---:|---|---:|---:|---:|---:|---:|"]
+             "HBM GB/s | DRAM share of read / write requests | VALU busy | L2 hit | "
+             "LDS conflicts / active LDS cycle |",
+             "|---|---|---:|---:|---|---:|---:|---|---:|---:|---:|"]
     for stage, e in kernels.items():
         mix = (f"{(e['rdreq'] - e['rdreq_64b'] - e['rdreq_32b']) / 1e6:.1f} / "
                f"{e['rdreq_64b'] / 1e6:.1f} / {e['rdreq_32b'] / 1e6:.1f}")
         lines.append(f"| {stage} | `{e['kernel']}` | {e['avg_ms'] or ''} | "
                      f"{e['hbm_read_bytes'] / 1e9:.2f} | {mix} | {e['hbm_write_bytes'] / 1e9:.2f} | "
-                     f"{e.get('hbm_GBps', '')} | {e['valu_busy']} | {e['tcc_hit_rate']} | "
+                     f"{e.get('hbm_GBps', '')} | {e['rdreq_dram_fraction']} / "
+                     f"{e['wrreq_dram_fraction']} | {e['valu_busy']} | {e['tcc_hit_rate']} | "
                      f"{e['lds_bank_conflict_per_active_lds_cycle']} |")
     lines += ["", f"Source digest of the counting sources: `{out['source_digest']}`. "
               "`bench.py` reports `traffic` from this file only while it matches.", ""]

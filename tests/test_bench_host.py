@@ -53,8 +53,19 @@ def test_counter_summary_rule_and_shapes(tmp_path):
             for k, v in c.items():
                 rows.append({"Dispatch_Id": i, "Grid_Size": grid, "Kernel_Name": name,
                              "Counter_Name": k, "Counter_Value": v})
+    p3 = []
+    for name, grid, i in disp:
+        copy = name == COPY and i > 0
+        c3 = {"TCC_EA0_RDREQ_DRAM_sum": 8388608 if copy else 600,
+              "TCC_EA0_WRREQ_DRAM_sum": 16777216 if copy else 300,
+              "TCC_EA0_RDREQ_sum": 8388608 if copy else 1000 + grid,
+              "TCC_EA0_WRREQ_sum": 16777216 if copy else 300}
+        for k, v in c3.items():
+            p3.append({"Dispatch_Id": i, "Grid_Size": grid, "Kernel_Name": name,
+                       "Counter_Name": k, "Counter_Value": v})
     _write(str(d / "pmc_1" / "host" / "run_counter_collection.csv"), p1)
     _write(str(d / "pmc_2" / "host" / "run_counter_collection.csv"), p2)
+    _write(str(d / "pmc_3" / "host" / "run_counter_collection.csv"), p3)
     trace = [{"Kernel_Name": name, "Grid_Size_X": grid, "Grid_Size_Y": 1, "Grid_Size_Z": 1,
               "Start_Timestamp": 0, "End_Timestamp": (3_000_000 if grid == 200 else 1_000_000)}
              for name, grid, _ in disp]
@@ -75,6 +86,7 @@ def test_counter_summary_rule_and_shapes(tmp_path):
     assert h["hbm_write_bytes"] == 64 * 100 + 32 * 200
     assert h["hbm_bytes_per_dispatch"] == h["hbm_read_bytes"] + h["hbm_write_bytes"]
     assert h["dispatches"] == 2 and h["rdreq_unsized"] == 0
+    assert h["rdreq_dram_fraction"] == 0.5 and h["wrreq_dram_fraction"] == 1.0
     assert out["source_digest"] == b.source_digest(b.COUNT_SOURCES)
     assert os.path.exists(tmp_path / "counters_rmat_s24.md")
 
