@@ -676,10 +676,11 @@ __global__ __launch_bounds__(1024) void k_mid_block(const int64_t *__restrict__ 
     if (lane == 0 && found) atomicAdd(tri_total, found);
 }
 
-// LDS bytes of k_mid_block16: the 2048-word bitmap, the pivot's counters
-// and the bitmap build's per-wavefront sums.
+// Dynamic LDS bytes of k_mid_block16: the pivot's counters and the bitmap
+// build's per-wavefront sums (the 2048-word bitmap is a static array, whose
+// address the compiler folds into each read's offset).
 __host__ __device__ __forceinline__ size_t mid_block16_bytes(int dmax) {
-    return 8 * (size_t)BITMAP16_WORDS + counter_bytes(dmax) + 64;
+    return counter_bytes(dmax) + 64;
 }
 
 // Workgroup pivots among the top 2^16 ranks (LK_BITMAP16).  One workgroup
@@ -695,12 +696,11 @@ __global__ __launch_bounds__(1024, 6) void k_mid_block16(
     const int32_t *__restrict__ item_v, const uint32_t *__restrict__ item_first, int64_t nitems,
     int dmax, int item_pairs, const uint16_t *__restrict__ ocol16, int32_t r16,
     uint32_t *__restrict__ osup, unsigned long long *__restrict__ tri_total) {
+    __shared__ uint2 bm[BITMAP16_WORDS];
     extern __shared__ uint4 lds4[];
     char *base = reinterpret_cast<char *>(lds4);
-    uint2 *bm = reinterpret_cast<uint2 *>(base);
-    uint32_t *lsup = reinterpret_cast<uint32_t *>(base + 8 * (size_t)BITMAP16_WORDS);
-    uint32_t *scan = reinterpret_cast<uint32_t *>(base + 8 * (size_t)BITMAP16_WORDS +
-                                                  counter_bytes(dmax));
+    uint32_t *lsup = reinterpret_cast<uint32_t *>(base);
+    uint32_t *scan = reinterpret_cast<uint32_t *>(base + counter_bytes(dmax));
     const int wpb = blockDim.x / TC_WAVE;
     const int wv = threadIdx.x / TC_WAVE;
     const int lane = __lane_id();
