@@ -59,7 +59,11 @@ from . import graphgen as gg
 from . import tc
 
 FAMILIES = ("er", "rmat", "ba")
-_REJECT = object()  # head request larger than the whole budget
+class _Reject:
+    """A request larger than the whole budget: answered with an error."""
+
+    def __init__(self, req):
+        self.req = req
 
 
 @dataclass
@@ -402,13 +406,20 @@ class Server:
         # admission step) under the lock
         self._mu = __import__("threading").Lock()
         self._used = 0
+        # cache keys whose graph a running unit is building
+        self.building = {}
         # key -> {"g": handle, "bytes": device bytes, "busy": bool}, oldest first
         self.resident = collections.OrderedDict()
         self.resident_bytes = 0
 
     def _evict_for(self, need, free_bytes):
         """Closes least recently used idle resident graphs until need bytes
-        fit; returns the new free byte count."""
+        fit; returns the new free byte count.  If closing every idle one
+        would not free enough, none is closed: the unit waits for running
+        units instead."""
+        idle = sum(e["bytes"] for e in self.resident.values() if not e["busy"])
+        if free_bytes + idle < need:
+            return free_bytes
         for key in list(self.resident):
             if free_bytes >= need:
                 break
@@ -423,17 +434,39 @@ class Server:
         return free_bytes
 
     def _form_unit(self, q, free_bytes):
-        """Next unit from the head of the queue, or None if it must wait."""
-        head = q[0]
-        if head.key is not None and head.key in self.resident:
-            e = self.resident[head.key]
-            if e["busy"]:
-                return None
-            self.resident.move_to_end(head.key)
-            return _Unit([head], 0, hit=e)
+        """Next unit to start, or None if none can start now.  Requests leave
+        the queue in arrival order, with two exceptions: a request whose
+        cache key is being built waits for that build (and then becomes a
+        resident hit) without holding up the requests behind it, and a
+        resident hit, which needs no device memory, may start ahead of a
+        build that waits for memory.  A build larger than the whole budget
+        comes back as a _Reject of that request."""
+        build_tried = False
+        for idx, r in enumerate(q):
+            if r.key is not None and r.key in self.building:
+                continue  # its graph is being built: answered from it later
+            if r.key is not None and r.key in self.resident:
+                e = self.resident[r.key]
+                if e["busy"]:
+                    continue
+                self.resident.move_to_end(r.key)
+                return _Unit([r], 0, hit=e)
+            if not build_tried:
+                build_tried = True
+                unit = self._form_build(q, idx, free_bytes)
+                if unit is not None:
+                    return unit
+                # the first build waits for memory: only resident hits pass it
+        return None
+
+    def _form_build(self, q, idx, free_bytes):
+        """The unit that starts with the build of q[idx] (with the queued
+        requests after it that batch with it), a _Reject, or None if it
+        must wait for memory."""
+        head = q[idx]
         est = max(estimate_bytes([head]), head.need)  # the exact need, once measured
         if est > self.cfg.budget_bytes:
-            return _REJECT
+            return _Reject(head)
         if est > free_bytes:
             free_bytes = self._evict_for(est, free_bytes)
             if est > free_bytes:
@@ -444,7 +477,7 @@ class Server:
         # fused launch, small ones a batched handle
         kind = "fused" if self._tiny(head) else "batch"
         reqs, pairs = [], 0
-        for r in q:
+        for r in q[idx:]:
             if (r.pairs >= self.cfg.small_pairs or pairs + r.pairs > self.cfg.batch_pairs
                     or not fused_ok(r) or self._tiny(r) != (kind == "fused") or r.solo
                     or r.need):
@@ -585,20 +618,25 @@ class Server:
                     with self._mu:
                         unit = self._form_unit(
                             q, self.cfg.budget_bytes - self._used - self.resident_bytes)
-                        if unit is not None and unit is not _REJECT:
+                        if isinstance(unit, _Unit):
                             self._used += unit.bytes
                             self.stats["peak_bytes"] = max(self.stats["peak_bytes"],
                                                            self._used + self.resident_bytes)
                     if unit is None:
                         break
-                    if unit is _REJECT:
-                        r = q.pop(0)
+                    if isinstance(unit, _Reject):
+                        r = unit.req
+                        q.remove(r)
                         finish(Reply(r.rid, None, "exceeds the device-memory budget",
                                      r.arrival, time.perf_counter() - t0, 1, r.pairs))
                         self.stats["rejected"] += 1
                         completed += 1
                         continue
-                    del q[:len(unit.reqs)]
+                    taken = {id(r) for r in unit.reqs}
+                    q[:] = [r for r in q if id(r) not in taken]
+                    if unit.hit is None and unit.reqs[0].key is not None:
+                        key = unit.reqs[0].key
+                        self.building[key] = self.building.get(key, 0) + 1
                     unit.stream_idx = free_streams.pop()
                     if unit.hit is not None:
                         unit.hit["busy"] = True
@@ -623,6 +661,11 @@ class Server:
                     continue
                 while True:
                     del in_flight[id(unit)]
+                    if unit.hit is None and unit.reqs[0].key is not None:
+                        key = unit.reqs[0].key
+                        self.building[key] -= 1
+                        if self.building[key] == 0:
+                            del self.building[key]
                     with self._mu:
                         self._used -= unit.bytes
                     free_streams.append(unit.stream_idx)

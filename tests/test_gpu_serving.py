@@ -292,6 +292,7 @@ def test_serving_resident_graphs_answer_later_queries(tclib):
     import dataclasses
     from paper_2105_00110_amd import serve
     base = serve.make_requests(6, seed=31, m_lo=2e3, m_hi=2e5, workers=6)
+    base.sort(key=lambda r: serve.estimate_bytes([r]))  # the largest graph is built last
     stream = torch.cuda.Stream()
     alone = [serve.run_alone(r, stream.cuda_stream) for r in base]
     rng = np.random.default_rng(31)
@@ -303,14 +304,28 @@ def test_serving_resident_graphs_answer_later_queries(tclib):
         else:
             q = ("vertices", rng.integers(0, base[i].n, 7))
         reqs.append(dataclasses.replace(base[i], rid=len(reqs), key=("g", i), query=q))
-    # the tight budget: twice the largest keyed request (keyed requests keep a
-    # handle, so their estimate is the handle path's)
-    for budget in (8 << 30, 2 * max(serve.estimate_bytes([r]) for r in reqs[:len(base)])):
+    # the tight budget: the largest keyed request's estimate (keyed requests
+    # keep a handle, so their estimate is the handle path's) plus half the
+    # bytes the other five graphs hold once resident, so that resident
+    # graphs must be evicted to build the largest, which comes last
+    held = []
+    for r in base:
+        _, g = serve.run_alone(r, stream.cuda_stream, keep=True)
+        held.append(g.device_bytes())
+        g.close()
+    tight = serve.estimate_bytes([reqs[len(base) - 1]]) + sum(held[:-1]) // 2
+    for budget in (8 << 30, tight):
         srv = serve.Server(serve.ServerConfig(budget_bytes=budget, streams=3))
-        replies = srv.run(reqs, serve.poisson_arrivals(len(reqs), 2000.0, seed=31))
+        # the six builds arrive first, 20 ms apart, then the queries
+        arrivals = np.concatenate([0.02 * np.arange(len(base)),
+                                   0.02 * len(base) + serve.poisson_arrivals(
+                                       len(reqs) - len(base), 2000.0, seed=31)])
+        replies = srv.run(reqs, arrivals)
         _say("resident serving, budget", budget, srv.stats)
         assert all(r.error is None for r in replies)
         assert srv.stats["resident_hits"] > 0
+        if budget == tight:
+            assert srv.stats["evictions"] > 0 and srv.stats["peak_bytes"] <= budget
         for rq, rp in zip(reqs, replies):
             i = rq.key[1]
             a = alone[i]

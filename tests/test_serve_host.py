@@ -70,6 +70,7 @@ def _server(monkeypatch, **cfg):
     s.resident_bytes = 0
     s._mu = threading.Lock()
     s._used = 0
+    s.building = {}
     return s
 
 
@@ -145,9 +146,33 @@ def test_form_unit_large_alone(monkeypatch):
 def test_form_unit_waits_and_rejects(monkeypatch):
     s = _server(monkeypatch, budget_bytes=10000, small_pairs=100, batch_pairs=250)
     assert s._form_unit([_R(0, 90)], 8000) is None         # fits the budget, not what is free
-    assert s._form_unit([_R(0, 101)], 10000) is serve._REJECT  # larger than the whole budget
+    rj = s._form_unit([_R(0, 101)], 10000)  # larger than the whole budget
+    assert isinstance(rj, serve._Reject) and rj.req.rid == 0
     u = s._form_unit([_R(0, 40), _R(1, 50)], 5000)          # the second would exceed free memory
     assert [r.rid for r in u.reqs] == [0]
+
+
+def test_request_waiting_for_its_graph_does_not_block(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250)
+    s.building = {("g", 1): 1}  # a unit is building graph ("g", 1)
+    q = [_R(0, 500, key=("g", 1), query=("topk", 5)), _R(1, 500)]
+    u = s._form_unit(q, 10**9)
+    assert [r.rid for r in u.reqs] == [1] and u.hit is None
+    s.building = {}
+    g = _G()
+    s.resident[("g", 1)] = {"g": g, "bytes": 10, "busy": False}
+    u = s._form_unit(q, 10**9)
+    assert [r.rid for r in u.reqs] == [0] and u.hit is s.resident[("g", 1)]
+
+
+def test_resident_hit_passes_a_build_waiting_for_memory(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10000, small_pairs=100, batch_pairs=250)
+    s.resident[("g", 2)] = {"g": _G(), "bytes": 0, "busy": False}
+    q = [_R(0, 90), _R(1, 90), _R(2, 5, key=("g", 2), query=("topk", 3))]
+    u = s._form_unit(q, 1000)  # the first build needs 9000
+    assert [r.rid for r in u.reqs] == [2] and u.hit is not None
+    # a later build does not pass the first one
+    assert s._form_unit(q[:2], 1000) is None
 
 
 def test_second_admission_grows_reservation_only_into_free_memory(monkeypatch):
@@ -175,7 +200,7 @@ def test_requeue_with_exact_need(monkeypatch):
     r2 = _R(4, 20)
     assert not s._requeue(serve._Unit([r2], 2000), serve.Requeue(10001), [])
     r2.need = 10001
-    assert s._form_unit([r2], 10000) is serve._REJECT
+    assert isinstance(s._form_unit([r2], 10000), serve._Reject)
 
 
 def test_requeue_of_a_batch_runs_each_alone(monkeypatch):
