@@ -661,7 +661,7 @@ def served_leg(args, autotune):
     out = {
         "workload": f"serve_mix_er_rmat_ba_m1e3-2e7_n{N}",
         "requests": N, "pairs": int(pairs),
-        "budget_gb": args.serve_budget_gb, "streams": args.serve_streams,
+        "budget_gb": args.serve_budget_gb, "streams": args.serve_streams, "hit_streams": cfg.hit_streams,
         "small_pairs": cfg.small_pairs, "batch_pairs": cfg.batch_pairs,
         "closed_loop": {"seconds": round(secs, 3), "graphs_per_s": capacity},
         "runs": [],
@@ -733,6 +733,12 @@ def resident_run(reqs, cfg, capacity):
     replies = srv.run(mix, serve.poisson_arrivals(len(mix), rate, seed=6))
     hits = [r for r in replies[K:] if r.error is None]
     builds = [r for r in replies[:K] if r.error is None]
+    slow = sorted(hits, key=lambda r: -r.latency)[:10]
+    last_build = max((r.arrival for r in builds), default=0.0)
+    log("served, resident graphs: slowest queries (arrival after the last build's "
+        "arrival in ms, latency in ms): "
+        + ", ".join(f"({1e3 * (r.arrival - last_build):.0f}, {1e3 * r.latency:.1f})"
+                    for r in slow))
     res = {"graphs": K, "queries": Q, "rate_per_s": round(rate, 2),
            "builds": {k: round(v, 3) for k, v in serve.latency_summary(builds).items()},
            "queries_on_resident": {k: round(v, 3) for k, v in serve.latency_summary(hits, 0.0).items()},

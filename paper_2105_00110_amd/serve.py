@@ -372,6 +372,9 @@ def estimate_bytes(reqs, kind="batch"):
 class ServerConfig:
     budget_bytes: int = 64 << 30
     streams: int = 4
+    # streams that only queries on resident graphs use: such a query takes
+    # well under a millisecond and should not wait for a running build
+    hit_streams: int = 1
     small_pairs: int = 1 << 17
     # requests below this many pairs go to the fused launch: one workgroup
     # per graph pays off for many tiny graphs at once, while a larger graph
@@ -398,7 +401,8 @@ class Server:
     def __init__(self, cfg=None):
         import torch
         self.cfg = cfg or ServerConfig()
-        self.streams = [torch.cuda.Stream() for _ in range(self.cfg.streams)]
+        self.streams = [torch.cuda.Stream()
+                        for _ in range(self.cfg.streams + self.cfg.hit_streams)]
         self.stats = {"units": 0, "batched_units": 0, "batched_requests": 0, "rejected": 0,
                       "peak_bytes": 0, "max_concurrent_units": 0, "resident_hits": 0,
                       "evictions": 0, "requeued": 0, "grown": 0}
@@ -433,15 +437,16 @@ class Server:
             self.stats["evictions"] += 1
         return free_bytes
 
-    def _form_unit(self, q, free_bytes):
+    def _form_unit(self, q, free_bytes, build=True):
         """Next unit to start, or None if none can start now.  Requests leave
         the queue in arrival order, with two exceptions: a request whose
         cache key is being built waits for that build (and then becomes a
         resident hit) without holding up the requests behind it, and a
         resident hit, which needs no device memory, may start ahead of a
-        build that waits for memory.  A build larger than the whole budget
-        comes back as a _Reject of that request."""
-        build_tried = False
+        build that waits for memory or, with build False (no build stream
+        is free), for a stream.  A build larger than the whole budget comes
+        back as a _Reject of that request."""
+        build_tried = not build
         for idx, r in enumerate(q):
             if r.key is not None and r.key in self.building:
                 continue  # its graph is being built: answered from it later
@@ -555,7 +560,9 @@ class Server:
             if source is not None:
                 source.release(rep.rid)
         q = []
-        free_streams = list(range(len(self.streams)))
+        # build streams, then the streams only resident hits take
+        free_streams = list(range(self.cfg.streams))
+        free_hit = list(range(self.cfg.streams, len(self.streams)))
         in_flight = {}
         self._used = 0
         done_q = queue.Queue()
@@ -588,8 +595,8 @@ class Server:
             done_q.put((unit, res, err, time.perf_counter() - t0, kept))
 
         try:
-            self._loop(pending, source, q, free_streams, in_flight, done_q, t0, work, finish,
-                       len(requests))
+            self._loop(pending, source, q, (free_streams, free_hit), in_flight, done_q, t0,
+                       work, finish, len(requests))
         finally:
             tc.tc_set_memory_limit(0)
         self.makespan = time.perf_counter() - t0
@@ -598,8 +605,10 @@ class Server:
             consumer.join()
         return replies
 
-    def _loop(self, pending, source, q, free_streams, in_flight, done_q, t0, work, finish, total):
-        """The dispatch loop of run()."""
+    def _loop(self, pending, source, q, free, in_flight, done_q, t0, work, finish, total):
+        """The dispatch loop of run(); free = (free build streams, free hit
+        streams)."""
+        free_streams, free_hit = free
         nxt = 0
         completed = 0
         with cf.ThreadPoolExecutor(max_workers=len(self.streams)) as ex:
@@ -614,10 +623,11 @@ class Server:
                     r.arrival = arr
                     q.append(r)
                     nxt += 1
-                while q and free_streams:
+                while q and (free_streams or free_hit):
                     with self._mu:
                         unit = self._form_unit(
-                            q, self.cfg.budget_bytes - self._used - self.resident_bytes)
+                            q, self.cfg.budget_bytes - self._used - self.resident_bytes,
+                            build=bool(free_streams))
                         if isinstance(unit, _Unit):
                             self._used += unit.bytes
                             self.stats["peak_bytes"] = max(self.stats["peak_bytes"],
@@ -637,7 +647,8 @@ class Server:
                     if unit.hit is None and unit.reqs[0].key is not None:
                         key = unit.reqs[0].key
                         self.building[key] = self.building.get(key, 0) + 1
-                    unit.stream_idx = free_streams.pop()
+                    unit.stream_idx = (free_hit.pop() if unit.hit is not None and free_hit
+                                       else free_streams.pop())
                     if unit.hit is not None:
                         unit.hit["busy"] = True
                         self.stats["resident_hits"] += 1
@@ -668,7 +679,8 @@ class Server:
                             del self.building[key]
                     with self._mu:
                         self._used -= unit.bytes
-                    free_streams.append(unit.stream_idx)
+                    (free_streams if unit.stream_idx < self.cfg.streams
+                     else free_hit).append(unit.stream_idx)
                     if unit.hit is not None:
                         unit.hit["busy"] = False
                     if kept is not None:

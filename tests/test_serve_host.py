@@ -175,6 +175,18 @@ def test_resident_hit_passes_a_build_waiting_for_memory(monkeypatch):
     assert s._form_unit(q[:2], 1000) is None
 
 
+def test_without_a_free_build_stream_only_resident_hits_start(monkeypatch):
+    s = _server(monkeypatch, budget_bytes=10**9, small_pairs=100, batch_pairs=250)
+    s.resident[("g", 2)] = {"g": _G(), "bytes": 0, "busy": False}
+    q = [_R(0, 90), _R(1, 90, key=("g", 5)), _R(2, 5, key=("g", 2), query=("topk", 3))]
+    # a build stream is free: the head builds first
+    assert [r.rid for r in s._form_unit(q, 10**9).reqs] == [0]
+    # only the hit stream is free: the hit behind both builds starts
+    u = s._form_unit(q, 10**9, build=False)
+    assert [r.rid for r in u.reqs] == [2] and u.hit is not None
+    assert s._form_unit(q[:2], 10**9, build=False) is None
+
+
 def test_second_admission_grows_reservation_only_into_free_memory(monkeypatch):
     s = _server(monkeypatch, budget_bytes=10000, small_pairs=100, batch_pairs=250)
     u = serve._Unit([_R(0, 20)], 2000)
