@@ -306,7 +306,7 @@ tc_status tc_count_bytes(tc_graph *g, const tc_tuning *tin, hipStream_t s, int64
         // row records and offsets, the 16-bit columns; temporaries of the
         // transposition sort, work-item lists, support reordering and
         // aggregation, all counted at once
-        b += 8 * m + 8 * (nn + 1) + 4 * words + 16 * nn + 8 * (nn + 1) + 2 * (m + 66) +
+        b += 8 * m + 8 * (nn + 1) + 4 * (words + 4) + 16 * nn + 8 * (nn + 1) + 2 * (m + 66) +
              30 * m + 96 * nn;
     } else {
         // flags, symmetric adjacency with its slot map; temporaries of the

@@ -793,16 +793,49 @@ __device__ __forceinline__ void planes_flush(uint32_t (&pl)[6], uint32_t (&cnt)[
     for (int k = 0; k < 6; ++k) pl[k] = 0;
 }
 
-// Rows of at most 64 entries, GL lanes each.  Row and column counts of a
-// row are added into the group's LDS counters (the GL lanes of a group sit
-// in one wavefront, so its LDS operations stay in program order), then
-// added to the support once per slot: no device-memory atomics.
+// Phase boundary of one wavefront's LDS counters: the lanes run in
+// lockstep, so a lane's LDS access after it sees every lane's access before
+// it; the fences and the wave barrier keep the compiler from moving LDS
+// accesses across it (no instruction is emitted).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Carry-save add of three bit vectors: s = a ^ b ^ c, cy = majority(a, b, c).
+__device__ __forceinline__ void csa(uint32_t a, uint32_t b, uint32_t c, uint32_t &s,
+                                    uint32_t &cy) {
+    const uint32_t u = a ^ b;
+    s = u ^ c;
+    cy = (a & b) | (u & c);
+}
+
+// The 32 bits of row i of B_u at the columns of stripe c (row i's bit b
+// is column i + 1 + b; bits outside the row read as 0).  lo/hi are the two
+// row words the stripe can touch, already loaded.
+__device__ __forceinline__ uint32_t stripe_bits(int o, uint32_t lo, uint32_t hi) {
+    if (o < 0) return lo << (int)(-o);
+    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)o & 31u);  // (hi:lo) >> (o mod 32)
+}
+
+// Rows of at most 64 entries, GL lanes each (GL a power of two, 16).
+// Row sums go to the group's LDS counters; for the column sums lane
+// (stripe c, row group g) walks rows g, g + G, ... of its stripe and adds
+// each row's 32 bits to byte counters: word s holds columns s, s + 8,
+// s + 16, s + 24 in its bytes (a column of such a row counts at most 63).
+// A butterfly over the G lanes of a stripe sums them, and one lane per
+// stripe adds the 32 counts to the LDS counters (each counter has one
+// writer), which are added to the support once per slot: no device-memory
+// atomics.  The GL lanes of a group sit in one wavefront and take the same
+// path up to the butterfly.
 template <int GL>
 __global__ __launch_bounds__(256) void k_fold(const int32_t *__restrict__ rows, int64_t nrows,
                                               const int64_t *__restrict__ orp,
                                               const int64_t *__restrict__ rowbase,
                                               const uint32_t *__restrict__ bits,
                                               uint32_t *__restrict__ osup) {
+    static_assert(GL >= 2 && GL <= TC_WAVE && (GL & (GL - 1)) == 0, "GL: a power of two");
     __shared__ uint32_t acc_all[256 / GL][64];
     const int sub = threadIdx.x % GL;
     uint32_t *acc = acc_all[threadIdx.x / GL];
@@ -822,70 +855,52 @@ __global__ __launch_bounds__(256) void k_fold(const int32_t *__restrict__ rows, 
             }
             acc[i] = c;
         }
-        const int nst = (d + 31) >> 5;
-        const int G = nst >= GL ? 1 : GL / nst;
-        for (int unit = sub; unit < nst * G; unit += GL) {
-            const int c = unit % nst, g = unit / nst;
-            uint32_t cnt[32];
-#pragma unroll
-            for (int b = 0; b < 32; ++b) cnt[b] = 0;
-            uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
-            int fill = 0;
-            const int imax = min(d - 2, 32 * c + 30);
-            for (int i = g; i <= imax; i += G) {
-                const int off = sd - bit_words_t<int>(d - i);
-                const int nw = (d - 1 - i + 31) >> 5;
-                const int o = 32 * c - (i + 1);  // row-i bit of the stripe's first column
-                uint32_t w;
-                if (o >= 0) {
-                    const int q = o >> 5;
-                    const int sh = o & 31;
-                    const uint32_t lo = q < nw ? rb[off + q] : 0u;
-                    const uint32_t hi = q + 1 < nw ? rb[off + q + 1] : 0u;
-                    w = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;
-                } else {
-                    w = nw > 0 ? rb[off] << (-o) : 0u;
-                }
-                uint32_t carry = w;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    const uint32_t tk = pl[k] & carry;
-                    pl[k] ^= carry;
-                    carry = tk;
-                }
-                if (++fill == 63) {
-                    planes_flush(pl, cnt);
-                    fill = 0;
-                }
+        wave_lds_sync();
+        const int nst = (d + 31) >> 5;  // 1 or 2 (a power of two)
+        const int G = GL / nst;
+        const int c = sub % nst, g = sub / nst;
+        uint32_t b8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int imax = min(d - 2, 32 * c + 30);
+        for (int i = g; i <= imax; i += G) {
+            const int off = sd - bit_words_t<int>(d - i);
+            const int nw = (d - 1 - i + 31) >> 5;
+            const int o = 32 * c - (i + 1);  // row-i bit of the stripe's first column
+            uint32_t w;
+            if (o >= 0) {
+                const int q = o >> 5;
+                const uint32_t lo = q < nw ? rb[off + q] : 0u;
+                const uint32_t hi = q + 1 < nw ? rb[off + q + 1] : 0u;
+                w = stripe_bits(o, lo, hi);
+            } else {
+                w = nw > 0 ? rb[off] << (-o) : 0u;
             }
-            planes_flush(pl, cnt);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) b8[t] += (w >> t) & 0x01010101u;
+        }
+        // lanes sub ^ m share the stripe for m = nst, 2 nst, ...; every
+        // group takes the same steps (m < nst: another stripe, not added)
+#pragma unroll
+        for (int m = 1; m < GL; m <<= 1)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const uint32_t y = __shfl_xor(b8[t], m, GL);
+                if (m >= nst) b8[t] += y;
+            }
+        if (g == 0) {
 #pragma unroll
             for (int b = 0; b < 32; ++b) {
                 const int j = 32 * c + b;
-                if (j < d && cnt[b]) atomicAdd(&acc[j], cnt[b]);
+                const uint32_t v = (b8[b & 7] >> (8 * (b >> 3))) & 0xFFu;
+                if (j < d && v) acc[j] += v;  // this lane is the column's only writer
             }
         }
+        wave_lds_sync();
         for (int j = sub; j < d; j += GL) {
             const uint32_t v = acc[j];
             if (v) osup[rs + j] += v;  // the group owns row u's slots here
         }
+        wave_lds_sync();  // before the next row's counters
     }
-}
-
-// Carry-save add of three bit vectors: s = a ^ b ^ c, cy = majority(a, b, c).
-__device__ __forceinline__ void csa(uint32_t a, uint32_t b, uint32_t c, uint32_t &s,
-                                    uint32_t &cy) {
-    const uint32_t u = a ^ b;
-    s = u ^ c;
-    cy = (a & b) | (u & c);
-}
-
-// The 32 bits of row i of B_u at the columns of stripe c (row i's bit b
-// is column i + 1 + b; bits outside the row read as 0).  lo/hi are the two
-// row words the stripe can touch, already loaded.
-__device__ __forceinline__ uint32_t stripe_bits(int o, uint32_t lo, uint32_t hi) {
-    if (o < 0) return lo << (int)(-o);
-    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)o & 31u);  // (hi:lo) >> (o mod 32)
 }
 
 // Big rows (|N_H(u)| > 64): one wavefront per row u.
@@ -894,43 +909,154 @@ __device__ __forceinline__ uint32_t stripe_bits(int o, uint32_t lo, uint32_t hi)
 //                of 64 stripes and walks the rows in order, so at every row
 //                the wavefront reads consecutive words (coalesced) and each
 //                word is fetched about once; the stripe's 32 columns sum in
-//                6 bit-sliced planes flushed to 32 counters every 63 rows.
-// Both sums land in the wavefront's LDS counters (each counter has one
-// owner at a time: plain adds) and are added to the support once.  Rows
-// longer than the LDS counters add to device memory with atomics instead.
+//                6 bit-sliced planes flushed to counters every 63 rows.
+// Both sums land in the wavefront's LDS counters and are added to the
+// support once.  Rows longer than the LDS counters add to device memory
+// with atomics instead.
 constexpr int FOLD_RC = 63;  // rows per flush: 6 counter planes hold up to 63
 
-// One row u of the big-row fold; rb = B_u's first word, sup = u's supports.
-// The LDS counter of column j sits at j + j / 32 (one pad word per 32): at a
-// flush, lane c adds to 33 c + b, so neighbouring stripes hit different
-// banks.
+// Rows of up to FOLD_PRIV_D entries (at most 32 stripes, so 64 / stripes
+// >= 2 lanes share each stripe) combine the lanes of a stripe through
+// private LDS partials: every lane stores its 16 counter words at
+// 17 lane + q (17 is odd: the 64 lanes of one store hit 64 banks), then
+// each column is summed by the one lane that owns it.
+constexpr int FOLD_PRIV_D = 1024;
+constexpr int FOLD_PRIV_WORDS = TC_WAVE * 17;
+
+// The 6 counter planes of a stripe (counts <= 63) added to 16 words of
+// 16-bit counters: word q holds column q (low half) and q + 16 (high
+// half).  Each plane is spread to bytes with one shift and one mask per
+// plane and byte offset s: byte t of v collects bit s + 8t of every plane
+// (bit k of the byte from plane k).
+__device__ __forceinline__ void planes_flush16(uint32_t (&pl)[6], uint32_t (&acc)[16]) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const uint32_t x = k >= s ? pl[k] << (k - s) : pl[k] >> (s - k);
+            v |= x & (0x01010101u << k);
+        }
+        acc[s] += v & 0x00FF00FFu;             // columns s, s + 16
+        acc[s + 8] += (v >> 8) & 0x00FF00FFu;  // columns s + 8, s + 24
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pl[k] = 0;
+}
+
+// The column walk of one lane: rows g, g + G, ... up to ilast of stripe c,
+// 8 rows per step into the planes pl, flush(pl) every 63 rows or fewer and
+// once at the end.
+template <typename I, typename Flush>
+__device__ __forceinline__ void stripe_walk(const uint32_t *__restrict__ rb, I d, I sd, I c,
+                                            I g, I G, bool active, I ilast,
+                                            uint32_t (&pl)[6], Flush flush) {
+    const I steps = (ilast + G) / G;  // rows per group, rounded up
+    int fill = 0;
+    for (I tb = 0; tb < steps; tb += 8) {
+        uint32_t lo[8], hi[8];
+        I oo[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const I i = g + G * (tb + e);
+            const I o = 32 * c - (i + 1);  // row bit of the stripe's column 0
+            lo[e] = 0u;
+            hi[e] = 0u;
+            oo[e] = -32;
+            if (active && i <= ilast && o > -32) {
+                const I off = sd - bit_words_t<I>(d - i);
+                const I nw = (d - 1 - i + 31) >> 5;
+                const I q = o < 0 ? 0 : (o >> 5);
+                oo[e] = o;
+                if (q < nw) lo[e] = rb[off + q];
+                if (o >= 0 && q + 1 < nw) hi[e] = rb[off + q + 1];
+            }
+        }
+        uint32_t w[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[e] = oo[e] > -32 ? stripe_bits((int)oo[e], lo[e], hi[e]) : 0u;
+        // the 8 rows into the planes by a carry-save tree: pl[0..2] are
+        // the ones, twos and fours of every column, and the one eights
+        // word of the step ripples into pl[3..5]
+        uint32_t t2a, t2b, t4a, t4b, e8;
+        csa(pl[0], w[0], w[1], pl[0], t2a);
+        csa(pl[0], w[2], w[3], pl[0], t2b);
+        csa(pl[1], t2a, t2b, pl[1], t4a);
+        csa(pl[0], w[4], w[5], pl[0], t2a);
+        csa(pl[0], w[6], w[7], pl[0], t2b);
+        csa(pl[1], t2a, t2b, pl[1], t4b);
+        csa(pl[2], t4a, t4b, pl[2], e8);
+#pragma unroll
+        for (int k = 3; k < 6; ++k) {
+            const uint32_t tk = pl[k] & e8;
+            pl[k] ^= e8;
+            e8 = tk;
+        }
+        fill += 8;
+        if (fill > FOLD_RC - 8) {
+            flush(pl);
+            fill = 0;
+        }
+    }
+    flush(pl);
+}
+
+// Row sums of B_u: lane i takes rows i, i + 64, ...; each lands in the LDS
+// counter of its slot (or in the support by atomic when not in LDS).  The
+// last slot has no row: it starts at 0.
 template <typename I>
-__device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I d, bool in_lds,
-                                             uint32_t *__restrict__ colc,
-                                             uint32_t *__restrict__ sup) {
-    const int lane = __lane_id();
-    const I sd = bit_words_t<I>(d);
-    // row sums (the last slot has no row: it starts at 0)
-    for (I i = lane; i < d; i += TC_WAVE) {
+__device__ __forceinline__ void fold_row_sums(const uint32_t *__restrict__ rb, I d, I sd,
+                                              bool in_lds, uint32_t *__restrict__ colc,
+                                              uint32_t *__restrict__ sup) {
+    for (I i = __lane_id(); i < d; i += TC_WAVE) {
         uint32_t c = 0;
         if (i < d - 1) {
             const I off = sd - bit_words_t<I>(d - i);
             const I nw = (d - 1 - i + 31) >> 5;
-            for (I q0 = 0; q0 < nw; q0 += 8) {
-                uint32_t x[8];
+            // aligned 16-byte loads from the row's first word rounded down:
+            // the up to 3 words before the row (inside the buffer, whose
+            // base is 16-byte aligned) and after it (inside its padding)
+            // are masked
+            const uint32_t *p = rb + off;
+            const I mis = (I)(((uintptr_t)p >> 2) & 3u);
+            const uint4 *pa = reinterpret_cast<const uint4 *>(p - mis);
+            const I tot = nw + mis;
+            for (I q0 = 0; q0 < tot; q0 += 8) {
+                const uint4 v0 = pa[q0 >> 2];
+                const uint4 v1 = q0 + 4 < tot ? pa[(q0 >> 2) + 1] : make_uint4(0u, 0u, 0u, 0u);
+                const uint32_t x[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-                for (int e = 0; e < 8; ++e) x[e] = q0 + e < nw ? rb[off + q0 + e] : 0u;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) c += __popc(x[e]);
+                for (int e = 0; e < 8; ++e)
+                    c += q0 + e >= mis && q0 + e < tot ? __popc(x[e]) : 0u;
             }
         }
         if (in_lds) colc[i + (i >> 5)] = c;
         else if (c) atomicAdd(&sup[i], c);
     }
-    // column sums: lane (stripe c, row group g) of a group of up to 64
-    // stripes; with fewer stripes than lanes the rows are dealt to
-    // G = 64 / stripes groups (row i to group i mod G), and the lanes of
-    // one group read consecutive words of one row at every step
+}
+
+// One row u of the big-row fold; rb = B_u's first word, sup = u's supports.
+// The LDS counter of column j sits at j + j / 32 (one pad word per 32), so
+// lanes that own neighbouring stripes hit different banks.
+//
+// Column sums: lane (stripe c, row group g) of a group of up to 64 stripes;
+// with fewer stripes than lanes the rows are dealt to G = 64 / stripes
+// groups (row i to group i mod G), and the lanes of one group read
+// consecutive words of one row at every step.
+//
+// Rows below FOLD_I32_MAX entries (I = int32_t) keep 16-bit counters (no
+// column of such a row reaches 2^15) and combine the G lanes of a stripe
+// through the private partials; longer rows keep 32 counters per lane and
+// add them by atomic.
+template <typename I>
+__device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I d, bool in_lds,
+                                             uint32_t *__restrict__ colc,
+                                             uint32_t *__restrict__ priv,
+                                             uint32_t *__restrict__ sup) {
+    const int lane = __lane_id();
+    const I sd = bit_words_t<I>(d);
+    fold_row_sums<I>(rb, d, sd, in_lds, colc, sup);
+    wave_lds_sync();
     const I nst = (d + 31) >> 5;
     for (I sg = 0; sg < nst; sg += TC_WAVE) {
         const I ns = min((I)TC_WAVE, nst - sg);
@@ -940,79 +1066,78 @@ __device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I 
         const bool active = g < G;
         // rows that reach some stripe of the group: i + 1 <= 32 (sg + ns - 1) + 31
         const I ilast = min(d - 2, 32 * (sg + ns) - 2);
-        const I steps = (ilast + G) / G;  // rows per group, rounded up
-        uint32_t cnt[32];
-#pragma unroll
-        for (int b = 0; b < 32; ++b) cnt[b] = 0;
         uint32_t pl[6] = {0, 0, 0, 0, 0, 0};
-        int fill = 0;
-        for (I tb = 0; tb < steps; tb += 8) {
-            uint32_t lo[8], hi[8];
-            I oo[8];
+        if constexpr (sizeof(I) == 4) {
+            uint32_t acc[16];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const I i = g + G * (tb + e);
-                const I o = 32 * c - (i + 1);  // row bit of the stripe's column 0
-                lo[e] = 0u;
-                hi[e] = 0u;
-                oo[e] = -32;
-                if (active && i <= ilast && o > -32) {
-                    const I off = sd - bit_words_t<I>(d - i);
-                    const I nw = (d - 1 - i + 31) >> 5;
-                    const I q = o < 0 ? 0 : (o >> 5);
-                    oo[e] = o;
-                    if (q < nw) lo[e] = rb[off + q];
-                    if (o >= 0 && q + 1 < nw) hi[e] = rb[off + q + 1];
+            for (int q = 0; q < 16; ++q) acc[q] = 0;
+            stripe_walk<I>(rb, d, sd, c, g, G, active, ilast, pl,
+                           [&](uint32_t (&p)[6]) { planes_flush16(p, acc); });
+            if (in_lds && d <= FOLD_PRIV_D) {
+                // one group (sg = 0): partials, then one owner per column
+#pragma unroll
+                for (int q = 0; q < 16; ++q) priv[17 * lane + q] = acc[q];
+                wave_lds_sync();
+                for (int u = lane; u < ns * 16; u += TC_WAVE) {
+                    const int cl = u >> 4, q = u & 15;
+                    uint32_t t = 0;
+                    for (int gg = 0; gg < G; ++gg) t += priv[17 * (gg * ns + cl) + q];
+                    const int j0 = 32 * cl + q, j1 = j0 + 16;
+                    if (j0 < d) colc[j0 + (j0 >> 5)] += t & 0xFFFFu;
+                    if (j1 < d) colc[j1 + (j1 >> 5)] += t >> 16;
+                }
+            } else if (active) {
+#pragma unroll
+                for (int h = 0; h < 32; ++h) {
+                    const I j = 32 * c + h;
+                    const uint32_t v = h < 16 ? acc[h] & 0xFFFFu : acc[h - 16] >> 16;
+                    if (j < d && v) {
+                        if (!in_lds) atomicAdd(&sup[j], v);
+                        else if (G == 1) colc[j + (j >> 5)] += v;  // its only owner
+                        else atomicAdd(&colc[j + (j >> 5)], v);
+                    }
                 }
             }
-            uint32_t w[8];
+        } else {
+            uint32_t cnt[32];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) w[e] = oo[e] > -32 ? stripe_bits((int)oo[e], lo[e], hi[e]) : 0u;
-            // the 8 rows into the planes by a carry-save tree: pl[0..2] are
-            // the ones, twos and fours of every column, and the one eights
-            // word of the step ripples into pl[3..5]
-            uint32_t t2a, t2b, t4a, t4b, e8;
-            csa(pl[0], w[0], w[1], pl[0], t2a);
-            csa(pl[0], w[2], w[3], pl[0], t2b);
-            csa(pl[1], t2a, t2b, pl[1], t4a);
-            csa(pl[0], w[4], w[5], pl[0], t2a);
-            csa(pl[0], w[6], w[7], pl[0], t2b);
-            csa(pl[1], t2a, t2b, pl[1], t4b);
-            csa(pl[2], t4a, t4b, pl[2], e8);
+            for (int b = 0; b < 32; ++b) cnt[b] = 0;
+            stripe_walk<I>(rb, d, sd, c, g, G, active, ilast, pl,
+                           [&](uint32_t (&p)[6]) { planes_flush(p, cnt); });
+            if (active) {
 #pragma unroll
-            for (int k = 3; k < 6; ++k) {
-                const uint32_t tk = pl[k] & e8;
-                pl[k] ^= e8;
-                e8 = tk;
-            }
-            fill += 8;
-            if (fill > FOLD_RC - 8) {
-                planes_flush(pl, cnt);
-                fill = 0;
-            }
-        }
-        planes_flush(pl, cnt);
-        if (active) {
-#pragma unroll
-            for (int b = 0; b < 32; ++b) {
-                const I j = 32 * c + b;
-                if (j < d && cnt[b]) {
-                    if (in_lds) atomicAdd(&colc[33 * c + b], cnt[b]);  // padded index of j
-                    else atomicAdd(&sup[j], cnt[b]);
+                for (int b = 0; b < 32; ++b) {
+                    const I j = 32 * c + b;
+                    if (j < d && cnt[b]) {
+                        if (in_lds) atomicAdd(&colc[j + (j >> 5)], cnt[b]);
+                        else atomicAdd(&sup[j], cnt[b]);
+                    }
                 }
             }
         }
+        wave_lds_sync();  // also: the next group's partials overwrite these
     }
     if (in_lds)
         for (I j = lane; j < d; j += TC_WAVE) {
             const uint32_t v = colc[j + (j >> 5)];
             if (v) sup[j] += v;  // the wavefront owns row u's slots here
         }
+    wave_lds_sync();  // before the next row's counters
 }
 
 // LDS words of one wavefront's column counters for rows up to dcap entries.
 __host__ __device__ __forceinline__ size_t fold_colc_words(int dcap) {
     return (size_t)dcap + ((size_t)dcap >> 5) + 1;
+}
+
+// Offset of the private partials in a wavefront's LDS words (after the
+// counters of the longest row that uses them), and the words per wavefront.
+__host__ __device__ __forceinline__ size_t fold_priv_off(int dcap) {
+    return fold_colc_words(dcap < FOLD_PRIV_D ? dcap : FOLD_PRIV_D);
+}
+__host__ __device__ __forceinline__ size_t fold_wave_words(int dcap) {
+    const size_t a = fold_colc_words(dcap), b = fold_priv_off(dcap) + FOLD_PRIV_WORDS;
+    return a > b ? a : b;
 }
 
 // One kernel per index type: rows below i32_max entries (I = int32_t; at
@@ -1027,7 +1152,8 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
                                                   int64_t i32_max) {
     extern __shared__ uint32_t colc_all[];
     const int wv = threadIdx.x / TC_WAVE;
-    uint32_t *colc = colc_all + (size_t)wv * fold_colc_words(dcap);
+    uint32_t *colc = colc_all + (size_t)wv * fold_wave_words(dcap);
+    uint32_t *priv = colc + fold_priv_off(dcap);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / TC_WAVE);
     for (int64_t gi = (int64_t)blockIdx.x * (blockDim.x / TC_WAVE) + wv; gi < nrows; gi += waves) {
         // the list is in rank order and the longest rows rank highest: take
@@ -1036,7 +1162,7 @@ __global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ ro
         const int64_t rs = orp[r];
         const int64_t d = orp[r + 1] - rs;
         if ((d < i32_max) != (sizeof(I) == 4)) continue;
-        fold_big_row<I>(bits + rowbase[r], (I)d, d <= dcap, colc, osup + rs);
+        fold_big_row<I>(bits + rowbase[r], (I)d, d <= dcap, colc, priv, osup + rs);
     }
 }
 
@@ -1284,7 +1410,9 @@ static tc_status bit_rows_prepare(tc_graph *g, hipStream_t s) {
     TC_HIP(hipMemcpyAsync(&words, g->rowbase + n, 8, hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
     g->bit_words = words;
-    TC_TRY(tc_graph_alloc(g, &g->hitbits, words, s));
+    // 4 words of padding: the fold's row sums read up to 3 words past a
+    // row's end
+    TC_TRY(tc_graph_alloc(g, &g->hitbits, words + 4, s));
     TC_TRY(tc_graph_alloc(g, &g->rowinfo, nn, s));
     if (n > 0) {
         k_row_info<<<grid_for(n), BK, 0, s>>>(n, g->orp, g->rowbase, g->rowinfo);
@@ -1479,7 +1607,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
         if (nb > 0) {
             int64_t fb = tc_div_up(nb, BK / TC_WAVE);
             // LDS counters for rows up to 7936 entries: 4 wavefronts x
-            // fold_colc_words(7936) words stay within 128 KB
+            // fold_wave_words(7936) words stay within 128 KB
             int dcap = g->max_dplus < 7936 ? g->max_dplus : 7936;
             dcap = (dcap + 3) & ~3;
             // TC_FOLD_I32_MAX (environment) lowers the row length from which
@@ -1490,7 +1618,7 @@ tc_status tc_count_mid(tc_graph *g, const tc_tuning &t, int lds_limit, int max_e
                 const long v = strtol(ev, nullptr, 10);
                 if (v >= 0 && v < FOLD_I32_MAX) i32_max = v;
             }
-            const size_t lds = (size_t)(BK / TC_WAVE) * fold_colc_words(dcap) * sizeof(uint32_t);
+            const size_t lds = (size_t)(BK / TC_WAVE) * fold_wave_words(dcap) * sizeof(uint32_t);
             k_fold_big<int32_t><<<(unsigned)(fb < 1048576 ? fb : 1048576), BK, lds, s>>>(
                 big, nb, g->orp, g->rowbase, g->hitbits, g->osup, dcap, i32_max);
             TC_LAUNCHED();
