@@ -919,9 +919,12 @@ constexpr int FOLD_RC = 63;  // rows per flush: 6 counter planes hold up to 63
 // >= 2 lanes share each stripe) combine the lanes of a stripe through
 // private LDS partials: every lane stores its 16 counter words at
 // 17 lane + q (17 is odd: the 64 lanes of one store hit 64 banks), then
-// each column is summed by the one lane that owns it.
+// each column is summed by the one lane that owns it.  Until the column walk
+// is over, the same words hold the first word of each row of B_u (written
+// with the row sums), which the walk reads in place of the closed form.
 constexpr int FOLD_PRIV_D = 1024;
 constexpr int FOLD_PRIV_WORDS = TC_WAVE * 17;
+static_assert(FOLD_PRIV_WORDS >= FOLD_PRIV_D, "the row offsets of such a row fit the same words");
 
 // The 6 counter planes of a stripe (counts <= 63) added to 16 words of
 // 16-bit counters: word q holds column q (low half) and q + 16 (high
@@ -947,9 +950,10 @@ __device__ __forceinline__ void planes_flush16(uint32_t (&pl)[6], uint32_t (&acc
 // The column walk of one lane: rows g, g + G, ... up to ilast of stripe c,
 // 8 rows per step into the planes pl, flush(pl) every 63 rows or fewer and
 // once at the end.
-template <typename I, typename Flush>
+template <typename I, bool TAB, typename Flush>
 __device__ __forceinline__ void stripe_walk(const uint32_t *__restrict__ rb, I d, I sd, I c,
                                             I g, I G, bool active, I ilast,
+                                            const uint32_t *__restrict__ rowoff,
                                             uint32_t (&pl)[6], Flush flush) {
     const I steps = (ilast + G) / G;  // rows per group, rounded up
     int fill = 0;
@@ -964,7 +968,9 @@ __device__ __forceinline__ void stripe_walk(const uint32_t *__restrict__ rb, I d
             hi[e] = 0u;
             oo[e] = -32;
             if (active && i <= ilast && o > -32) {
-                const I off = sd - bit_words_t<I>(d - i);
+                I off;
+                if constexpr (TAB) off = (I)rowoff[i];
+                else off = sd - bit_words_t<I>(d - i);
                 const I nw = (d - 1 - i + 31) >> 5;
                 const I q = o < 0 ? 0 : (o >> 5);
                 oo[e] = o;
@@ -1007,11 +1013,13 @@ __device__ __forceinline__ void stripe_walk(const uint32_t *__restrict__ rb, I d
 template <typename I>
 __device__ __forceinline__ void fold_row_sums(const uint32_t *__restrict__ rb, I d, I sd,
                                               bool in_lds, uint32_t *__restrict__ colc,
+                                              uint32_t *__restrict__ rowoff,
                                               uint32_t *__restrict__ sup) {
     for (I i = __lane_id(); i < d; i += TC_WAVE) {
         uint32_t c = 0;
         if (i < d - 1) {
             const I off = sd - bit_words_t<I>(d - i);
+            if (rowoff) rowoff[i] = (uint32_t)off;
             const I nw = (d - 1 - i + 31) >> 5;
             // aligned 16-byte loads from the row's first word rounded down:
             // the up to 3 words before the row (inside the buffer, whose
@@ -1055,7 +1063,12 @@ __device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I 
                                              uint32_t *__restrict__ sup) {
     const int lane = __lane_id();
     const I sd = bit_words_t<I>(d);
-    fold_row_sums<I>(rb, d, sd, in_lds, colc, sup);
+    // rows that combine through the private partials keep their first
+    // word's offset in the same LDS words until the walk is over
+    uint32_t *rowoff = nullptr;
+    if constexpr (sizeof(I) == 4)
+        if (in_lds && d <= FOLD_PRIV_D) rowoff = priv;
+    fold_row_sums<I>(rb, d, sd, in_lds, colc, rowoff, sup);
     wave_lds_sync();
     const I nst = (d + 31) >> 5;
     for (I sg = 0; sg < nst; sg += TC_WAVE) {
@@ -1071,10 +1084,15 @@ __device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I 
             uint32_t acc[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[q] = 0;
-            stripe_walk<I>(rb, d, sd, c, g, G, active, ilast, pl,
-                           [&](uint32_t (&p)[6]) { planes_flush16(p, acc); });
+            const auto flush16 = [&](uint32_t (&p)[6]) { planes_flush16(p, acc); };
+            if (rowoff)
+                stripe_walk<I, true>(rb, d, sd, c, g, G, active, ilast, rowoff, pl, flush16);
+            else
+                stripe_walk<I, false>(rb, d, sd, c, g, G, active, ilast, nullptr, pl, flush16);
             if (in_lds && d <= FOLD_PRIV_D) {
-                // one group (sg = 0): partials, then one owner per column
+                // one group (sg = 0): partials (over the row offsets, read by
+                // every lane before this point), then one owner per column
+                wave_lds_sync();
 #pragma unroll
                 for (int q = 0; q < 16; ++q) priv[17 * lane + q] = acc[q];
                 wave_lds_sync();
@@ -1102,8 +1120,8 @@ __device__ __forceinline__ void fold_big_row(const uint32_t *__restrict__ rb, I 
             uint32_t cnt[32];
 #pragma unroll
             for (int b = 0; b < 32; ++b) cnt[b] = 0;
-            stripe_walk<I>(rb, d, sd, c, g, G, active, ilast, pl,
-                           [&](uint32_t (&p)[6]) { planes_flush(p, cnt); });
+            stripe_walk<I, false>(rb, d, sd, c, g, G, active, ilast, nullptr, pl,
+                                  [&](uint32_t (&p)[6]) { planes_flush(p, cnt); });
             if (active) {
 #pragma unroll
                 for (int b = 0; b < 32; ++b) {
@@ -1144,7 +1162,7 @@ __host__ __device__ __forceinline__ size_t fold_wave_words(int dcap) {
 // most FOLD_I32_MAX) or from it up (int64_t); each skips the other's rows of
 // the list.
 template <typename I>
-__global__ __launch_bounds__(256) void k_fold_big(const int32_t *__restrict__ rows, int64_t nrows,
+__global__ __launch_bounds__(256, 4) void k_fold_big(const int32_t *__restrict__ rows, int64_t nrows,
                                                   const int64_t *__restrict__ orp,
                                                   const int64_t *__restrict__ rowbase,
                                                   const uint32_t *__restrict__ bits,
