@@ -170,7 +170,7 @@ __global__ void k_item_write(int32_t n, const uint32_t *__restrict__ cnt,
 //              test, and the bit-field reads take their offset and width
 //              from the value's low 5 bits.  Values at or below v's own
 //              hold no bits.  A probe reads the packed pairs of entries as
-//              loaded; a miss adds 0 to the lane's spare counter.
+//              loaded; only hits add to the counters.
 // ---------------------------------------------------------------------------
 constexpr int LK_HASH = 0, LK_GLOBAL = 1, LK_BITMAP = 2, LK_BITMAP16 = 3;
 constexpr int BITMAP16_WORDS = 2048;
@@ -259,12 +259,12 @@ __device__ void bitmap_build(uint2 *bm, uint32_t *scan, const int32_t *__restric
 // aligned words hold the 32 entries from c0 (an odd c0 starts in the upper
 // half of the first); each aligned pair is probed as loaded: the lower entry
 // is the word's low 16 bits, whose low 5 bits the bit-field reads take as
-// they are, the upper entry its high 16 bits.  Every hit adds 1 to the
-// counter of its place in the pivot's row; an entry past the tail adds its
-// bit to the lane's spare counter, which is never read.
+// they are, the upper entry its high 16 bits.  Every hit inside the tail
+// adds 1 to the counter of its place in the pivot's row: only those lanes
+// take part in the LDS add (a lane mask, not a select of a spare counter:
+// the select cost a VALU instruction per entry).
 __device__ __forceinline__ uint32_t bitmap16_run(const uint16_t *__restrict__ ocol16, int64_t c0,
-                                                 int cnt, const uint2 *bm, uint32_t *lsup,
-                                                 int spare) {
+                                                 int cnt, const uint2 *bm, uint32_t *lsup) {
     const uint32_t *o32 = reinterpret_cast<const uint32_t *>(ocol16);
     const int64_t q = c0 >> 1;
     const uint32_t sh = (uint32_t)(c0 & 1) << 4;
@@ -292,7 +292,7 @@ __device__ __forceinline__ uint32_t bitmap16_run(const uint16_t *__restrict__ oc
             const uint32_t bit = __builtin_amdgcn_ubfe(w[e].x, key[e], 1u);
             const uint32_t at =
                 w[e].y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w[e].x, 0u, key[e]));
-            atomicAdd(&lsup[bit != 0u && k < cnt ? (int)at : spare], bit);
+            if (bit != 0u && k < cnt) atomicAdd(&lsup[at], 1u);
             mask |= bit << k;
         }
     }
@@ -714,7 +714,6 @@ __global__ __launch_bounds__(1024, 6) void k_mid_block16(
         // 2048 words over the 16-bit values, that is ranks r16 .. r16 + 2^16 - 1
         for (int j = threadIdx.x; j < d; j += blockDim.x) lsup[j] = 0;
         bitmap_build(bm, scan, ocol, vstart, d, (uint32_t)r16, 32u * BITMAP16_WORDS);
-        const int spare = d + lane;
         for (int64_t g0 = first + (int64_t)wv * TC_WAVE; g0 < pend; g0 += (int64_t)wpb * TC_WAVE) {
             // this lane's pair: scan start, tail length, bit-row base and
             // word count (a row below 2^16 entries has fewer than 2^11
@@ -754,7 +753,7 @@ __global__ __launch_bounds__(1024, 6) void k_mid_block16(
                 if (x < total) {
                     const int cnt = min(32, tl - 32 * kw);
                     const uint32_t mask =
-                        bitmap16_run(ocol16, (int64_t)st + 32 * kw, cnt, bm, lsup, spare);
+                        bitmap16_run(ocol16, (int64_t)st + 32 * kw, cnt, bm, lsup);
                     bits[gb + kw] = mask;
                     found += (unsigned long long)__popc(mask);
                 }
