@@ -508,10 +508,20 @@ class Graph:
         return out
 
     def results_device(self):
-        """Device copies as torch tensors (int64 views of the uint64 data)."""
+        """Device copies as torch tensors (int64 views of the uint64 data),
+        ready for use on the caller's current stream.
+
+        The library copies on the handle's stream.  When that is not the
+        current stream, the handle's stream first waits for the current one
+        (the new tensors' memory may still be in use there) and the current
+        stream then waits for the copies."""
         import torch
         n, m, G = self.n, self.m, self.num_graphs
         dev = torch.device("cuda")
+        cur = torch.cuda.current_stream()
+        own = None
+        if self.stream is not None and int(self.stream) != int(cur.cuda_stream):
+            own = torch.cuda.ExternalStream(int(self.stream))
         out = {
             "tri": torch.empty(max(n, 1), dtype=torch.int64, device=dev),
             "support": torch.empty(max(m, 1), dtype=torch.int64, device=dev),
@@ -519,8 +529,12 @@ class Graph:
             "num": torch.empty(max(n, 1), dtype=torch.int64, device=dev),
             "tc": torch.empty(max(n, 1), dtype=torch.float64, device=dev),
         }
+        if own is not None:
+            own.wait_stream(cur)
         tc_get_results(self.h, _ptr(out["tri"]), _ptr(out["support"]), _ptr(out["triG"]),
                        _ptr(out["num"]), _ptr(out["tc"]), TC_MEM_DEVICE, self.stream)
+        if own is not None:
+            cur.wait_stream(own)
         return out
 
     def numerator_algebraic(self):

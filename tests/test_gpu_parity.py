@@ -75,6 +75,35 @@ def test_parity_small_families(tclib, name):
     assert_parity(run_gpu(tclib, src, dst, n, device=False), ref)
 
 
+def test_device_results_on_another_stream(tclib):
+    """Graph.results_device() of a handle whose stream is not the current
+    one: the tensors are complete on the current stream even while the
+    handle's stream is still busy (long fills are queued there before the
+    copies), and equal the oracle's results."""
+    src, dst, n = gg.rmat(14, 16, seed=5)
+    ref = native.o1_definition(src, dst, n)
+    side = torch.cuda.Stream()
+    s = torch.as_tensor(np.ascontiguousarray(src, np.int32)).cuda()
+    d = torch.as_tensor(np.ascontiguousarray(dst, np.int32)).cuda()
+    side.wait_stream(torch.cuda.current_stream())
+    g = tclib.Graph.from_edges(s, d, n, stream=side.cuda_stream)
+    g.compute()
+    busy = torch.empty(1 << 28, device="cuda")
+    busy.record_stream(side)
+    with torch.cuda.stream(side):
+        for _ in range(20):
+            busy.fill_(1.0)
+    _say("device results on another stream, n", n)
+    r = g.results_device()
+    got = {k: v.cpu().numpy() for k, v in r.items()}  # on the current stream
+    g.close()
+    np.testing.assert_array_equal(got["support"][:ref.m].view(np.uint64), ref.sup)
+    np.testing.assert_array_equal(got["tri"][:n].view(np.uint64), ref.tri)
+    np.testing.assert_array_equal(got["num"][:n].view(np.uint64), ref.num)
+    np.testing.assert_array_equal(got["tc"][:n].view(np.uint64), ref.tc.view(np.uint64))
+    assert int(got["triG"][0]) == ref.triG
+
+
 @pytest.mark.parametrize("fname", ["fig2_worked_example.txt", "fig1a.txt", "fig1c.txt",
                                    "fig1d.txt"])
 def test_parity_paper_figures(tclib, fname):
