@@ -387,6 +387,19 @@ def current_stream():
     return torch.cuda.current_stream().cuda_stream
 
 
+def _streams(stream):
+    """(torch's current stream, the handle's stream as a torch stream, or
+    None when it is the current one).  Device tensors made on the current
+    stream and used by the library on another need both orders: the
+    library's work after the current stream's, and the caller's later work
+    after the library's."""
+    import torch
+    cur = torch.cuda.current_stream()
+    if stream is None or int(stream) == int(cur.cuda_stream):
+        return cur, None
+    return cur, torch.cuda.ExternalStream(int(stream))
+
+
 class Graph:
     """A libtc handle.  Build with ``from_edges`` / ``from_csr`` / ``batch``."""
 
@@ -405,6 +418,9 @@ class Graph:
             dst = dst.to(torch.int32).contiguous()
             if stream is None:
                 stream = current_stream()
+            _, own = _streams(stream)
+            if own is not None:  # the pairs (and their conversion) are on the current stream
+                own.wait_stream(torch.cuda.current_stream())
         else:
             src = np.ascontiguousarray(src, np.int32)
             dst = np.ascontiguousarray(dst, np.int32)
@@ -418,6 +434,9 @@ class Graph:
         if dev:
             if stream is None:
                 stream = current_stream()
+            cur, own = _streams(stream)
+            if own is not None:
+                own.wait_stream(cur)
         else:
             row_ptr = np.ascontiguousarray(row_ptr, np.int64)
             col = np.ascontiguousarray(col, np.int32)
@@ -439,6 +458,10 @@ class Graph:
         dev = _is_torch(src) and src.is_cuda
         if dev and stream is None:
             stream = current_stream()
+        if dev:
+            cur, own = _streams(stream)
+            if own is not None:
+                own.wait_stream(cur)
         if not dev:
             src = np.ascontiguousarray(src, np.int32)
             dst = np.ascontiguousarray(dst, np.int32)
@@ -518,10 +541,7 @@ class Graph:
         import torch
         n, m, G = self.n, self.m, self.num_graphs
         dev = torch.device("cuda")
-        cur = torch.cuda.current_stream()
-        own = None
-        if self.stream is not None and int(self.stream) != int(cur.cuda_stream):
-            own = torch.cuda.ExternalStream(int(self.stream))
+        cur, own = _streams(self.stream)
         out = {
             "tri": torch.empty(max(n, 1), dtype=torch.int64, device=dev),
             "support": torch.empty(max(m, 1), dtype=torch.int64, device=dev),
@@ -628,6 +648,18 @@ class FusedBatch:
         self.ws_ptr = self.workspace.data_ptr() + off
 
     def run(self):
+        """One launch on ``stream``.  When that is not torch's current
+        stream, the launch waits for the current stream (where the buffers
+        were made) and the current stream waits for the launch."""
+        cur, own = _streams(self.stream)
+        if own is not None:
+            own.wait_stream(cur)
+        st = self._launch()
+        if own is not None:
+            cur.wait_stream(own)
+        return st
+
+    def _launch(self):
         return tc_batch_fused(
             _ptr(self.src), _ptr(self.dst), _ptr(self.pair_off), _ptr(self.vtx_off),
             _ptr(self.order), self.G, self.P, self.N, _ptr(self.eu), _ptr(self.ev),
@@ -639,6 +671,9 @@ class FusedBatch:
         """Host copies: dict(eu, ev, support, num_edges, tri, triG, num, tc, status)
         with the C layout (edges at the pair offsets)."""
         P, N, G = self.P, self.N, self.G
+        cur, own = _streams(self.stream)
+        if own is not None:  # the copies below run on the current stream
+            cur.wait_stream(own)
         out = {"eu": self.eu[:P], "ev": self.ev[:P], "support": self.support[:P],
                "num_edges": self.num_edges[:G], "tri": self.tri[:N], "triG": self.triG[:G],
                "num": self.num[:N], "tc": self.tc[:N], "status": self.status[:G]}

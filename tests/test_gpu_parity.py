@@ -104,6 +104,28 @@ def test_device_results_on_another_stream(tclib):
     assert int(got["triG"][0]) == ref.triG
 
 
+def test_device_pairs_from_another_stream(tclib):
+    """Graph.from_edges of device pairs made on the current stream, with a
+    handle on another stream: the build waits for the pairs (their copy is
+    queued behind long fills), and the results equal the oracle's."""
+    src, dst, n = gg.rmat(14, 16, seed=5)
+    ref = native.o1_definition(src, dst, n)
+    side = torch.cuda.Stream()
+    busy = torch.empty(1 << 28, device="cuda")
+    for _ in range(20):
+        busy.fill_(1.0)
+    s = torch.as_tensor(np.ascontiguousarray(src, np.int32)).cuda()
+    d = torch.as_tensor(np.ascontiguousarray(dst, np.int32)).cuda()
+    _say("device pairs from another stream, n", n)
+    g = tclib.Graph.from_edges(s, d, n, stream=side.cuda_stream)
+    st = g.compute()
+    res = g.results()
+    res["eu"], res["ev"] = g.edges()
+    res["status"], res["m"] = st, g.m
+    g.close()
+    assert_parity(res, ref)
+
+
 @pytest.mark.parametrize("fname", ["fig2_worked_example.txt", "fig1a.txt", "fig1c.txt",
                                    "fig1d.txt"])
 def test_parity_paper_figures(tclib, fname):
