@@ -12,6 +12,8 @@ void emu_launch(unsigned grid, unsigned block, std::function<void()> fn) {
     blockDim.x = block;
     for (unsigned b = 0; b < grid; ++b) {
         EmuBlock blk;
+        std::barrier<> bar((std::ptrdiff_t)block);
+        blk.bar = &bar;
         for (unsigned w = 0; w < (block + TC_WAVE - 1) / TC_WAVE; ++w) blk.waves.push_back(new EmuWave());
         emu_blk = &blk;
         std::vector<std::thread> th;
